@@ -1,0 +1,194 @@
+"""Benchmark of the multi-rhs HISQ Dslash and the even-odd CG solvers on one MI355X.
+
+Workload (default): the 32^3 x 8 lattice with 16 complex Gaussian right-hand sides, FP32 Dslash
+(FP32 links, complex64 vectors), seeded synthetic links (exp(i 0.4 H) + 0.05 G fat links, -1/24
+Haar SU(3) Naik links).  One step = one full-lattice multi-rhs Dslash w = D v for the bundle:
+the two half Dslash launches D_oe (even -> odd) and D_eo (odd -> even).
+value = Gflop/s under the 1146 flop per site per rhs convention (Section 1, Table 1 model).
+
+Also reported on the same JSON line:
+  roofline      : compulsory HBM bytes per half-Dslash launch / average launch time (HIP events
+                  on the launch stream), against 8 TB/s;
+  dslash_sweep  : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
+  cg            : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
+                  the mixed-precision solver (FP16 links) and the plain FP64 solver;
+  cpu_baseline  : the FP64 numpy oracle's half Dslash on a bounded sample of the same lattice.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-sweep]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup):
+    """Time `steps` full Dslash applications; returns (ms per step, mean ms per launch)."""
+    for _ in range(warmup):
+        lat.dslash(1, prec, v_e, w_o)
+        lat.dslash(0, prec, v_o, w_e)
+    torch.cuda.synchronize()
+    ev = [_events(torch) for _ in range(2 * steps)]
+    t0, t1 = _events(torch)
+    t0.record()
+    for k in range(steps):
+        ev[2 * k][0].record()
+        lat.dslash(1, prec, v_e, w_o)
+        ev[2 * k][1].record()
+        ev[2 * k + 1][0].record()
+        lat.dslash(0, prec, v_o, w_e)
+        ev[2 * k + 1][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    per_launch = [a.elapsed_time(b) for a, b in ev]
+    return t0.elapsed_time(t1) / steps, float(np.mean(per_launch))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver works on a single device (the multi-GPU "
+              "design is rhs-bundle sharding, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1409_1510_amd import hisq
+    from paper_1409_1510_amd import perfmodel as pm
+
+    torch.cuda.set_device(0)
+    cfg = synth.WORKLOADS["c1"]
+    dims, n = cfg["dims"], args.nrhs
+    seed = synth.workload_seed("c1")
+    fat, naik = synth.gauge_links(dims, seed, eps=cfg["eps"])
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
+    vh = lat.vh
+    v = synth.sources(dims, n, seed + 1)
+    v_e = torch.from_numpy(v).to("cuda:0").to(torch.complex64)
+    v_o = torch.from_numpy(synth.sources(dims, n, seed + 2)).to("cuda:0").to(torch.complex64)
+    w_e = torch.empty_like(v_e)
+    w_o = torch.empty_like(v_o)
+
+    ms_step, ms_launch = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
+                                            args.steps, args.warmup)
+    flops_step = 2 * pm.half_dslash_flops(vh, n)
+    gflops = flops_step / (ms_step * 1e-3) / 1e9
+    bytes_launch = pm.half_dslash_bytes(vh, n, hisq.HISQ_F32)
+    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
+    result = {
+        "metric": "multi-rhs Dslash HBM GB/s & Gflop/s; CG s/rhs to 1e-8 vs plain FP64 CG",
+        "value": round(gflops, 1),
+        "unit": "Gflop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Dslash-only throughput, {'x'.join(map(str, dims))} lattice, "
+                               f"{n} complex Gaussian rhs, FP32 links and vectors, full 18-real "
+                               "Naik links; step = D_oe + D_eo (whole-lattice D on the bundle)",
+                   "lattice": list(dims), "n_rhs": n, "flop_per_site_rhs": pm.FLOP_PER_SITE_RHS},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_dslash<float,float2,RT,false,false> (half Dslash, FP32)",
+                     "bytes_per_launch": bytes_launch, "ms_per_launch": round(ms_launch, 5)},
+    }
+
+    if not args.no_sweep:
+        sweep = []
+        for prec, recon, name in ((hisq.HISQ_F64, 18, "f64"), (hisq.HISQ_F32, 18, "f32"),
+                                  (hisq.HISQ_F32, 14, "f32_r14"), (hisq.HISQ_F16, 18, "f16links"),
+                                  (hisq.HISQ_F16, 14, "f16links_r14")):
+            if recon == 14:
+                lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 14)
+            for nn in (1, 2, 4, 8, 16):
+                dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
+                a = torch.from_numpy(synth.sources(dims, nn, 9)).to("cuda:0").to(dt)
+                b = torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0").to(dt)
+                ms, ml = dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a),
+                                            torch.empty_like(b), 10, 3)
+                byt = pm.half_dslash_bytes(vh, nn, prec, recon)
+                lb, vb = pm.PREC_BYTES[prec]
+                paper_b = vh * (pm.link_reals(recon if prec else 18) * lb + nn * 17 * 6 * vb)
+                sweep.append({"prec": name, "n": nn, "ms_per_launch": round(ml, 5),
+                              "gflops": round(pm.half_dslash_flops(vh, nn) / (ml * 1e-3) / 1e9, 1),
+                              "compulsory_GBps": round(byt / (ml * 1e-3) / 1e9, 1),
+                              "paper_model_GBps": round(paper_b / (ml * 1e-3) / 1e9, 1)})
+            if recon == 14:
+                lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
+        result["dslash_sweep"] = sweep
+
+    if not args.no_cg:
+        c2 = synth.WORKLOADS["c2"]
+        fat2, naik2 = synth.gauge_links(c2["dims"], synth.workload_seed("c2"), eps=c2["eps"])
+        lat2 = hisq.Lattice(c2["dims"], 0)
+        lat2.load_links(fat2, naik2)
+        b = torch.from_numpy(synth.sources(c2["dims"], c2["n"], synth.workload_seed("c2") + 1)).to("cuda:0")
+        cg = {"workload": "32x32x32x8, m=0.02, 8 complex Gaussian rhs, tol 1e-8 (true FP64 residual)"}
+        for name, kw in (("mixed_f16links", dict(kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)),
+                         ("mixed_f32links", dict(kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F32)),
+                         ("plain_f64", dict(kind=hisq.HISQ_CG_F64))):
+            x, info = lat2.cg(c2["mass"], b, tol=c2["tol"], max_iter=40000, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = lat2.cg(c2["mass"], b, tol=c2["tol"], max_iter=40000, **kw)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            cg[name] = {"s_per_rhs": round(sec / c2["n"], 5), "seconds": round(sec, 4),
+                        "iters_max": max(info["iters"]), "iters_min": min(info["iters"]),
+                        "reliable_updates": info["reliable_updates"],
+                        "true_resid_max": max(info["true_resid"]), "rc": info["rc"],
+                        "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
+        cg["speedup_mixed_vs_f64"] = round(cg["plain_f64"]["seconds"] / cg["mixed_f16links"]["seconds"], 3)
+        result["cg"] = cg
+        lat2.close()
+
+    if not args.no_cpu:
+        import oracle
+        nthreads = 1
+        vs = v[:1]
+        t = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t < 12.0 or reps < 1:
+            oracle.dslash_half(fat, naik, vs, dims, 1)
+            reps += 1
+        sec = time.perf_counter() - t
+        result["cpu_baseline"] = {
+            "value": round(reps * pm.half_dslash_flops(vh, 1) / sec / 1e9, 3), "unit": "Gflop/s",
+            "cores": nthreads, "kind": "oracle",
+            "sample": f"{reps} FP64 numpy-oracle half Dslash applications (1 rhs) on the same "
+                      f"32^3x8 links, {sec:.1f} s; single-threaded numpy"}
+    lat.close()
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,157 @@
+/*
+ * hisq.h -- C ABI of the MI355X (gfx950) multi-right-hand-side HISQ Dslash and even-odd CG.
+ *
+ * Operator (Kaczmarek et al., "HISQ inverter on Intel Xeon Phi and NVIDIA GPUs", Section 1,
+ * Eq. 3; several right-hand sides at once as in Eq. 4):
+ *
+ *   w(x) = sum_{mu=0..3} [ X(x,mu) v(x+mu) - X(x-mu,mu)^dag v(x-mu)
+ *                        + N(x,mu) v(x+3mu) - N(x-3mu,mu)^dag v(x-3mu) ]
+ *
+ * on a periodic lattice of extents dims = {Lx, Ly, Lz, Lt} (each even, >= 4).  Staggered phases
+ * and boundary signs are folded into the links X (fat) and N (Naik) by the caller.  D only
+ * couples sites of opposite parity (parity = (x+y+z+t) mod 2), D = [[0, D_eo], [D_oe, 0]], and
+ * the solver works on the even-site normal operator M = m^2 - D_eo D_oe (Hermitian positive
+ * definite because D_eo = -D_oe^dag).
+ *
+ * Layouts (all little-endian, no padding):
+ *   links  : [V][4][3][3] complex128 (re, im interleaved), sites in lexicographic order
+ *            lex = x + Lx*(y + Ly*(z + Lz*t)), direction mu = 0..3 is x, y, z, t, each 3x3
+ *            matrix row-major.  V = Lx*Ly*Lz*Lt.
+ *   vectors: [n][3][V/2] complex (complex128 for HISQ_F64, complex64 otherwise) on the sites of
+ *            one parity: right-hand side major, then colour, then site; the site index within a
+ *            parity is lex >> 1.  Right-hand side i of a bundle is therefore a pointer offset of
+ *            i*3*(V/2) complex elements.
+ *
+ * Ownership and streams: every vector pointer is device memory owned by the caller.  The
+ * context copies the links on hisq_load_links (the caller may free its buffers afterwards) and
+ * owns its workspace.  Work is enqueued on the context's HIP stream; hisq_dslash_mrhs,
+ * hisq_apply_m and hisq_dot_mrhs return without synchronising, hisq_cg_mrhs and the network
+ * training/evaluation calls synchronise before returning.  A context is not thread-safe.
+ *
+ * Errors: every int-returning call returns HISQ_OK (0) or a negative code and never throws;
+ * hisq_last_error() gives the message of the context's last failing call.
+ */
+#ifndef HISQ_H
+#define HISQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HISQ_OK = 0,
+  HISQ_ERR_ARG = -1,       /* bad argument: dims, null pointer, n out of range, bad enum      */
+  HISQ_ERR_STATE = -2,     /* call out of order, e.g. no links loaded / no network initialised */
+  HISQ_ERR_HIP = -3,       /* HIP runtime failure; message holds the hipError string          */
+  HISQ_ERR_OOM = -4,       /* device allocation failed                                        */
+  HISQ_ERR_NOCONV = -5,    /* a right-hand side missed tol; x and the stats are still valid   */
+  HISQ_ERR_NONFINITE = -6, /* non-finite input or breakdown of the iteration                  */
+  HISQ_ERR_IO = -7         /* file could not be read or written                               */
+};
+
+/* Precision of a Dslash application: vectors complex128 + FP64 links (HISQ_F64); vectors
+ * complex64 + FP32 links (HISQ_F32); vectors complex64 + FP16 link storage, FP32 arithmetic
+ * (HISQ_F16). */
+enum { HISQ_F64 = 0, HISQ_F32 = 1, HISQ_F16 = 2 };
+
+/* Bit mask of link copies hisq_load_links builds. */
+enum { HISQ_LINKS_F64 = 1, HISQ_LINKS_F32 = 2, HISQ_LINKS_F16 = 4, HISQ_LINKS_ALL = 7 };
+
+/* Solver kinds of hisq_cg_mrhs. */
+enum { HISQ_CG_F64 = 0, HISQ_CG_MIXED = 1, HISQ_FCG_NN = 2 };
+
+#define HISQ_MAX_RHS 64
+
+typedef struct hisq_ctx hisq_ctx;
+
+/* Create a context for a lattice of extents dims on HIP device `device`, enqueueing on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  Returns HISQ_ERR_ARG for odd extents or
+ * extents below 4, HISQ_ERR_HIP if the device cannot be selected. */
+int hisq_create(hisq_ctx **ctx, const int dims[4], int device, void *hip_stream);
+
+/* Free the context, its link copies and its workspace.  NULL is accepted. */
+int hisq_destroy(hisq_ctx *ctx);
+
+/* Message of the last failing call on this context ("" if none); NULL ctx gives the message of
+ * the last failing hisq_create.  The pointer stays valid until the next call on the context. */
+const char *hisq_last_error(const hisq_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int hisq_set_stream(hisq_ctx *ctx, void *hip_stream);
+
+/* Copy the fat links X and Naik links N (Section 1, Eq. 3) into the context.
+ *   fat, naik : [V][4][3][3] complex128, host or device memory (detected), read only.
+ *   copies    : HISQ_LINKS_* mask of device copies to build (FP64 is needed by HISQ_F64 calls
+ *               and by the FP64 parts of every solver).
+ *   naik_recon: 18 (store all 18 reals) or 14 (store rows 0 and 1 of N plus one complex scale
+ *               z, row 2 = z * conj(row0 x row1); Section 1 and Section 2 name the 14-float
+ *               Naik reconstruction).  r14 applies to the FP32 and FP16 copies; it is exact for
+ *               N = c * U with U in U(3), and the call fails with HISQ_ERR_ARG if the given Naik
+ *               links are not of that form (relative reconstruction error above 1e-10).
+ * Non-finite link entries give HISQ_ERR_NONFINITE.  Replaces earlier links. */
+int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *naik, int copies, int naik_recon);
+
+/* Multi-rhs half Dslash (Section 1, Eq. 3 and Eq. 4): out = D_{out_parity, 1-out_parity} in.
+ *   out_parity: 1 gives D_oe (even -> odd), 0 gives D_eo (odd -> even).
+ *   prec      : HISQ_F64 / HISQ_F32 / HISQ_F16 (see above; the matching link copy must exist).
+ *   n         : number of right-hand sides, 1..HISQ_MAX_RHS.
+ *   in        : device [n][3][V/2] complex on parity 1-out_parity.
+ *   out       : device [n][3][V/2] complex on out_parity; must not alias in.
+ * The links are read once per site for all n right-hand sides.  Each output is bit-identical to
+ * the output of n separate single-rhs calls.  Asynchronous on the context stream. */
+int hisq_dslash_mrhs(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *out);
+
+/* Even-site normal operator out = m^2 in - D_eo (D_oe in) for n right-hand sides (the operator
+ * of the even-odd CG).  in/out: device [n][3][V/2] complex on even sites, not aliased.  If
+ * pq_out is not NULL it receives (device, n doubles) Re<in, out> per right-hand side,
+ * accumulated in FP64.  Asynchronous. */
+int hisq_apply_m(hisq_ctx *ctx, int prec, double mass, int n, const void *in, void *out, double *pq_out);
+
+/* Per-rhs inner products dots[i] = <a_i, b_i> = sum conj(a) b over the 3*V/2 components of one
+ * parity, accumulated in FP64 (deterministic fixed-order tree).  a, b: device [n][3][V/2]
+ * complex of precision prec (HISQ_F64: complex128, else complex64).  dots: device, 2*n doubles
+ * (re, im).  Asynchronous. */
+int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, const void *b, double *dots);
+
+typedef struct {
+  int kind;           /* HISQ_CG_F64, HISQ_CG_MIXED or HISQ_FCG_NN                              */
+  double tol;         /* stop rhs i when ||b_i - M x_i|| / ||b_i|| <= tol, checked in FP64         */
+  int max_iter;       /* iteration cap per right-hand side                                       */
+  int reliable_every; /* MIXED/FCG: FP64 true-residual replacement interval in iterations (50)   */
+  int link_prec;      /* MIXED/FCG inner operator: HISQ_F32 or HISQ_F16                            */
+  int use_x0;         /* 1: x holds the initial guess on entry; 0: start from x = 0                */
+  int check_every;    /* host poll interval of the per-rhs residuals, iterations (0 = default 8)  */
+} hisq_cg_params;
+
+typedef struct {
+  int *iters;          /* [n] iterations done for each rhs (caller-allocated, may be NULL)      */
+  double *true_resid;  /* [n] final FP64 ||b - Mx|| / ||b|| (caller-allocated, may be NULL)     */
+  int *converged;      /* [n] 1 if rhs i met tol (caller-allocated, may be NULL)                */
+  int *fell_back;      /* [n] FCG: 1 if rhs i switched to the mixed solver (may be NULL)         */
+  int total_iters;     /* iterations of the bundle loop                                          */
+  int reliable_updates;/* FP64 residual replacements done                                        */
+  long long dslash_site_rhs; /* sum over half-Dslash launches of (sites x active rhs)           */
+  double seconds;      /* wall time of the solve                                                 */
+  size_t peak_bytes;   /* device workspace held by the context after the solve                   */
+} hisq_cg_stats;
+
+/* Solve M x_i = b_i (M = m^2 - D_eo D_oe on even sites) for n right-hand sides at once; each
+ * rhs has its own CG scalars and stops individually (Section 2: the remaining linear algebra
+ * is kept separate per rhs so converged rhs can stop).
+ *   b : device [n][3][V/2] complex128, even sites.   x : device [n][3][V/2] complex128.
+ *   HISQ_CG_F64   : FP64 throughout.
+ *   HISQ_CG_MIXED : FP32 Dslash/BLAS body (links p->link_prec), FP64 solution accumulation, FP64
+ *                   reductions, FP64 true-residual replacement every p->reliable_every iterations.
+ *   HISQ_FCG_NN   : flexible CG preconditioned by the network of hisq_nn_init/hisq_nn_train;
+ *                   falls back to MIXED for a rhs whose preconditioned step breaks down.
+ * Synchronises.  Returns HISQ_ERR_NOCONV if some rhs missed tol within max_iter. */
+int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
+                 const hisq_cg_params *p, hisq_cg_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISQ_H */

@@ -1,0 +1,505 @@
+// Multi-rhs reductions and the CG linear algebra for gfx950.
+//
+// Every per-rhs reduction is a deterministic two-stage tree in FP64: each workgroup reduces its
+// elements (per thread in a fixed order, then 64-lane shuffles, then the 4 waves in a fixed
+// order) into one partial per (rhs, workgroup); a second kernel sums the partials of a rhs in a
+// fixed order.  No atomics, so results are reproducible run to run.
+//
+// The CG kernels act on a bundle of n right-hand sides with separate scalars per rhs and skip a
+// rhs whose `active` flag is 0 (Section 2: the linear algebra is kept separate per rhs so that
+// converged rhs stop).  Vectors are [n][3][V/2] complex; a rhs is a contiguous run of 3*V/2
+// complex numbers.
+#include "internal.hpp"
+#include "cg_state.hpp"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 4;  // complex elements per thread in the streaming kernels
+constexpr int kPerBlock = kThreads * kItems;
+
+__device__ inline double block_sum(double v, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return s;
+}
+
+// res[row] = sum_b partial[row * nblk + b], rows = n * width.
+__global__ void __launch_bounds__(kThreads)
+k_reduce_rows(const double *__restrict__ partial, int nblk, double *__restrict__ res) {
+  __shared__ double red[4];
+  const int row = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(row) * nblk + b];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) res[row] = v;
+}
+
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_dot_partials(const C *__restrict__ a, const C *__restrict__ b, unsigned len, int nblk,
+               double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  const size_t off = size_t(r) * len;
+  double re = 0.0, im = 0.0;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C u = a[off + j], v = b[off + j];
+      re = fma(double(u.x), double(v.x), re);
+      re = fma(double(u.y), double(v.y), re);
+      im = fma(double(u.x), double(v.y), im);
+      im = fma(-double(u.y), double(v.x), im);
+    }
+  }
+  re = block_sum(re, red);
+  im = block_sum(im, red);
+  if (threadIdx.x == 0) {
+    partial[size_t(2 * r) * nblk + blockIdx.x] = re;
+    partial[size_t(2 * r + 1) * nblk + blockIdx.x] = im;
+  }
+}
+
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_norm2_partials(const C *__restrict__ a, unsigned len, int nblk, double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  const size_t off = size_t(r) * len;
+  double v = 0.0;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C u = a[off + j];
+      v = fma(double(u.x), double(u.x), v);
+      v = fma(double(u.y), double(u.y), v);
+    }
+  }
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// CG kernels.  S: device CGState (per-rhs scalars and flags).
+
+__global__ void k_reduce_alpha(const double *__restrict__ partial, int nblk, CGState *S) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  if (!S->active[r]) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    S->pq[r] = v;
+    if (!(v > 0.0) || !isfinite(v)) {  // M is HPD: <p, Mp> <= 0 means breakdown
+      S->alpha[r] = 0.0;
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+    } else {
+      S->alpha[r] = S->rho[r] / v;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; partials of ||r||^2.
+template <typename C, typename CX>
+__global__ void __launch_bounds__(kThreads)
+k_update_xr(CX *__restrict__ x, C *__restrict__ rv, const C *__restrict__ p, const C *__restrict__ q,
+            unsigned len, int nblk, const CGState *S, double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  using R = decltype(C{}.x);
+  using RX = decltype(CX{}.x);
+  const R a = R(S->alpha[r]);
+  const RX ax = RX(S->alpha[r]);
+  const size_t off = size_t(r) * len;
+  double rr = 0.0;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C pj = p[off + j], qj = q[off + j], rj = rv[off + j];
+      CX xj = x[off + j];
+      xj.x = fma(ax, RX(pj.x), xj.x);
+      xj.y = fma(ax, RX(pj.y), xj.y);
+      rj.x = fma(-a, qj.x, rj.x);
+      rj.y = fma(-a, qj.y, rj.y);
+      x[off + j] = xj;
+      rv[off + j] = rj;
+      rr = fma(double(rj.x), double(rj.x), rr);
+      rr = fma(double(rj.y), double(rj.y), rr);
+    }
+  }
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = rr;
+}
+
+__global__ void k_reduce_beta(const double *__restrict__ partial, int nblk, CGState *S, double tol2) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  if (!S->active[r]) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    S->iters[r] += 1;
+    if (!isfinite(v)) {
+      S->beta[r] = 0.0;
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+      return;
+    }
+    S->beta[r] = v / S->rho[r];
+    S->rho[r] = v;
+    S->rr[r] = v;
+    if (v <= tol2 * S->bnorm2[r]) S->hit[r] = 1;
+  }
+}
+
+// p = r + beta p
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_update_p(const C *__restrict__ rv, C *__restrict__ p, unsigned len, const CGState *S) {
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  using R = decltype(C{}.x);
+  const R b = R(S->beta[r]);
+  const size_t off = size_t(r) * len;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C pj = p[off + j], rj = rv[off + j];
+      pj.x = fma(b, pj.x, rj.x);
+      pj.y = fma(b, pj.y, rj.y);
+      p[off + j] = pj;
+    }
+  }
+}
+
+// sel[r] = active[r] && (all || hit[r])
+__global__ void k_select(CGState *S, int n, int all) {
+  const int r = threadIdx.x;
+  if (r < n) S->sel[r] = S->active[r] && (all || S->hit[r]);
+}
+
+// x64 += xhat; xhat = 0 for the rhs selected by mask.
+__global__ void __launch_bounds__(kThreads)
+k_accum_x(double2 *__restrict__ x, float2 *__restrict__ xh, unsigned len, const int *mask) {
+  const int r = blockIdx.y;
+  if (!mask[r]) return;
+  const size_t off = size_t(r) * len;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      double2 xj = x[off + j];
+      float2 h = xh[off + j];
+      xj.x += double(h.x);
+      xj.y += double(h.y);
+      x[off + j] = xj;
+      xh[off + j] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// r = b - mx for selected rhs (FP64), stored in the body precision, and ||r||^2 partials.
+// With copy_p, also p = r (restart).
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_replace_r(const double2 *__restrict__ b, const double2 *__restrict__ mx, C *__restrict__ rv,
+            C *__restrict__ p, unsigned len, int nblk, const CGState *S, const int *sel,
+            double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (!sel[r]) return;
+  using R = decltype(C{}.x);
+  const size_t off = size_t(r) * len;
+  double rr = 0.0;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      double2 bj = b[off + j], mj = mx[off + j];
+      double re = bj.x - mj.x, im = bj.y - mj.y;
+      rr = fma(re, re, rr);
+      rr = fma(im, im, rr);
+      C o;
+      o.x = R(re);
+      o.y = R(im);
+      if (rv) rv[off + j] = o;
+      if (p) p[off + j] = o;
+    }
+  }
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = rr;
+}
+
+// After a true-residual recomputation of the selected rhs: converged ones stop, the others
+// continue with rho = ||r_true||^2.  final_only: only record rr_true.
+__global__ void k_reduce_true(const double *__restrict__ partial, int nblk, CGState *S, double tol2,
+                              int final_only) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  if (!(final_only ? S->fin[r] : S->sel[r])) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    S->rr_true[r] = v;
+    if (final_only) return;
+    S->hit[r] = 0;
+    S->replacements[r] += 1;
+    if (!isfinite(v)) {
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+    } else if (v <= tol2 * S->bnorm2[r]) {
+      S->status[r] = CG_CONVERGED;
+      S->active[r] = 0;
+    } else {
+      S->rho[r] = v;
+      S->rr[r] = v;
+    }
+  }
+}
+
+// ||b||^2 partials for all rhs (sel = null) and the initialisation of the per-rhs state.
+__global__ void k_init_state(const double *__restrict__ partial, int nblk, CGState *S, int n) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    S->bnorm2[r] = v;
+    S->iters[r] = 0;
+    S->hit[r] = 0;
+    S->replacements[r] = 0;
+    S->alpha[r] = S->beta[r] = 0.0;
+    S->rr_true[r] = 0.0;
+    S->fin[r] = 1;
+    if (!isfinite(v)) {
+      S->status[r] = CG_NONFINITE;
+      S->active[r] = 0;
+    } else if (v == 0.0) {
+      S->status[r] = CG_CONVERGED;
+      S->active[r] = 0;
+    } else {
+      S->status[r] = CG_RUNNING;
+      S->active[r] = 1;
+    }
+  }
+}
+
+// rho = ||r||^2 from partials for active rhs (start of an iteration sequence).
+__global__ void k_set_rho(const double *__restrict__ partial, int nblk, CGState *S, double tol2) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  if (!S->sel[r]) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) {
+    S->rho[r] = v;
+    S->rr[r] = v;
+    S->rr_true[r] = v;
+    if (v <= tol2 * S->bnorm2[r]) {  // the initial guess already solves it
+      S->status[r] = CG_CONVERGED;
+      S->active[r] = 0;
+    }
+  }
+}
+
+// zero the selected rhs of a vector (x = 0 for b = 0, or xhat = 0)
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_zero_sel(C *__restrict__ v, unsigned len, const int *sel, int invert) {
+  const int r = blockIdx.y;
+  if (sel && (bool(sel[r]) == bool(invert))) return;
+  const size_t off = size_t(r) * len;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C z;
+      z.x = 0;
+      z.y = 0;
+      v[off + j] = z;
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// host launchers
+
+int blas_nblk(const hisq_ctx *ctx) { return (3 * ctx->g.vh + kPerBlock - 1) / kPerBlock; }
+
+int launch_reduce_partials(hisq_ctx *ctx, const double *partial, int n, int nblk, int width,
+                           double *res) {
+  k_reduce_rows<<<n * width, kThreads, 0, ctx->stream>>>(partial, nblk, res);
+  LAUNCHCHK(ctx, "k_reduce_rows");
+  return HISQ_OK;
+}
+
+int launch_dot_partials(hisq_ctx *ctx, int prec, int n, const void *a, const void *b,
+                        double *partial, int *nblk_out) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  dim3 grid(nblk, n);
+  if (prec == HISQ_F64)
+    k_dot_partials<double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<const double2 *>(a), static_cast<const double2 *>(b), len, nblk, partial);
+  else
+    k_dot_partials<float2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<const float2 *>(a), static_cast<const float2 *>(b), len, nblk, partial);
+  LAUNCHCHK(ctx, "k_dot_partials");
+  *nblk_out = nblk;
+  return HISQ_OK;
+}
+
+extern "C" int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, const void *b,
+                             double *dots) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!a || !b || !dots) return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: null pointer");
+  if (!prec_valid(prec)) return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: bad precision %d", prec);
+  if (n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: n = %d outside 1..%d", n, HISQ_MAX_RHS);
+  const int nblk = blas_nblk(ctx);
+  void *pp;
+  RETCHK(ws_get(ctx, WS_PARTIAL, size_t(2 * n) * nblk * sizeof(double), &pp));
+  double *partial = static_cast<double *>(pp);
+  int nb;
+  RETCHK(launch_dot_partials(ctx, prec, n, a, b, partial, &nb));
+  return launch_reduce_partials(ctx, partial, n, nb, 2, dots);
+}
+
+// ---- CG building blocks used by cg.cpp ----
+
+int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n) {
+  k_reduce_alpha<<<n, kThreads, 0, ctx->stream>>>(partial, nblk, S);
+  LAUNCHCHK(ctx, "k_reduce_alpha");
+  return HISQ_OK;
+}
+
+int cg_update_xr(hisq_ctx *ctx, int body_prec, bool x64, void *x, void *r, const void *p,
+                 const void *q, CGState *S, int n, double *partial) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  dim3 grid(nblk, n);
+  if (body_prec == HISQ_F64)
+    k_update_xr<double2, double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(x), static_cast<double2 *>(r), static_cast<const double2 *>(p),
+        static_cast<const double2 *>(q), len, nblk, S, partial);
+  else if (x64)
+    k_update_xr<float2, double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(x), static_cast<float2 *>(r), static_cast<const float2 *>(p),
+        static_cast<const float2 *>(q), len, nblk, S, partial);
+  else
+    k_update_xr<float2, float2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<float2 *>(x), static_cast<float2 *>(r), static_cast<const float2 *>(p),
+        static_cast<const float2 *>(q), len, nblk, S, partial);
+  LAUNCHCHK(ctx, "k_update_xr");
+  return HISQ_OK;
+}
+
+int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2) {
+  k_reduce_beta<<<n, kThreads, 0, ctx->stream>>>(partial, blas_nblk(ctx), S, tol2);
+  LAUNCHCHK(ctx, "k_reduce_beta");
+  return HISQ_OK;
+}
+
+int cg_update_p(hisq_ctx *ctx, int body_prec, const void *r, void *p, const CGState *S, int n) {
+  const unsigned len = 3u * ctx->g.vh;
+  dim3 grid(blas_nblk(ctx), n);
+  if (body_prec == HISQ_F64)
+    k_update_p<double2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(r),
+                                                            static_cast<double2 *>(p), len, S);
+  else
+    k_update_p<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<const float2 *>(r),
+                                                           static_cast<float2 *>(p), len, S);
+  LAUNCHCHK(ctx, "k_update_p");
+  return HISQ_OK;
+}
+
+int cg_select(hisq_ctx *ctx, CGState *S, int n, int all) {
+  k_select<<<1, 64, 0, ctx->stream>>>(S, n, all);
+  LAUNCHCHK(ctx, "k_select");
+  return HISQ_OK;
+}
+
+int cg_accum_x(hisq_ctx *ctx, void *x64, void *xh32, const int *mask, int n) {
+  dim3 grid(blas_nblk(ctx), n);
+  k_accum_x<<<grid, kThreads, 0, ctx->stream>>>(static_cast<double2 *>(x64), static_cast<float2 *>(xh32),
+                                                3u * ctx->g.vh, mask);
+  LAUNCHCHK(ctx, "k_accum_x");
+  return HISQ_OK;
+}
+
+int cg_replace_r(hisq_ctx *ctx, int body_prec, const void *b, const void *mx, void *r, void *p,
+                 const CGState *S, const int *sel, int n, double *partial) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  dim3 grid(nblk, n);
+  const double2 *b2 = static_cast<const double2 *>(b), *m2 = static_cast<const double2 *>(mx);
+  if (body_prec == HISQ_F64)
+    k_replace_r<double2><<<grid, kThreads, 0, ctx->stream>>>(
+        b2, m2, static_cast<double2 *>(r), static_cast<double2 *>(p), len, nblk, S, sel, partial);
+  else
+    k_replace_r<float2><<<grid, kThreads, 0, ctx->stream>>>(
+        b2, m2, static_cast<float2 *>(r), static_cast<float2 *>(p), len, nblk, S, sel, partial);
+  LAUNCHCHK(ctx, "k_replace_r");
+  return HISQ_OK;
+}
+
+int cg_reduce_true(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2, int final_only) {
+  k_reduce_true<<<n, kThreads, 0, ctx->stream>>>(partial, blas_nblk(ctx), S, tol2, final_only);
+  LAUNCHCHK(ctx, "k_reduce_true");
+  return HISQ_OK;
+}
+
+int cg_init_state(hisq_ctx *ctx, const void *b, CGState *S, int n, double *partial) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  dim3 grid(nblk, n);
+  k_norm2_partials<double2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(b),
+                                                                len, nblk, partial);
+  LAUNCHCHK(ctx, "k_norm2_partials");
+  k_init_state<<<n, kThreads, 0, ctx->stream>>>(partial, nblk, S, n);
+  LAUNCHCHK(ctx, "k_init_state");
+  return HISQ_OK;
+}
+
+int cg_set_rho(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2) {
+  k_set_rho<<<n, kThreads, 0, ctx->stream>>>(partial, blas_nblk(ctx), S, tol2);
+  LAUNCHCHK(ctx, "k_set_rho");
+  return HISQ_OK;
+}
+
+int cg_zero(hisq_ctx *ctx, int prec, void *v, const int *sel, int invert, int n) {
+  const unsigned len = 3u * ctx->g.vh;
+  dim3 grid(blas_nblk(ctx), n);
+  if (prec == HISQ_F64)
+    k_zero_sel<double2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<double2 *>(v), len, sel, invert);
+  else
+    k_zero_sel<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<float2 *>(v), len, sel, invert);
+  LAUNCHCHK(ctx, "k_zero_sel");
+  return HISQ_OK;
+}

@@ -1,0 +1,254 @@
+// Host drivers of the multi-rhs even-odd CG solvers.
+//
+// The whole solve stays on the device; the host enqueues the iteration and only looks at the
+// per-rhs residual state at polls (Section 2 keeps the solver on the GPU and moves only the set
+// of residuals to the host per iteration; here a poll every `check_every` iterations, with the
+// per-rhs decisions taken on the device between polls).
+//
+// Plain FP64 CG: textbook CG per rhs on M = m^2 - D_eo D_oe.  When a rhs's iterated residual
+// drops below tol its true residual is recomputed in FP64; it stops if that meets tol and
+// restarts from its current x otherwise.
+//
+// Mixed precision: FP32 Dslash (FP32 or FP16 link storage) and FP32 vectors in the body, FP64
+// solution x, FP64 reductions, and every `reliable_every` iterations (and whenever a rhs's
+// iterated residual reaches tol) a reliable update: x += xhat in FP64, r = b - M x with FP64
+// links, the body residual replaced by (float) r, xhat = 0, search direction kept (Sleijpen and
+// van der Vorst 1996).  A rhs stops when its FP64 true residual meets tol.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "cg_state.hpp"
+#include "internal.hpp"
+
+int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hisq_cg_params *p,
+                 hisq_cg_stats *st, CGState *S, CGState *hS, double *partial);
+
+namespace {
+
+struct Vecs {
+  void *r = nullptr, *p = nullptr, *q = nullptr, *t = nullptr, *xh = nullptr;
+  void *mx64 = nullptr, *t64 = nullptr;
+};
+
+int poll(hisq_ctx *ctx, CGState *S, CGState *hS) {
+  HIPCHK(ctx, hipMemcpyAsync(hS, S, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return HISQ_OK;
+}
+
+// mx64 = M x64 (FP64 links) for the rhs selected by mask.
+int apply_m64(hisq_ctx *ctx, double mass, int n, const void *x64, void *t64, void *mx64,
+              const int *mask) {
+  RETCHK(launch_dslash(ctx, 1, HISQ_F64, n, x64, t64, false, 0.0, nullptr, nullptr, nullptr, mask));
+  RETCHK(launch_dslash(ctx, 0, HISQ_F64, n, t64, mx64, true, mass * mass, x64, nullptr, nullptr, mask));
+  return HISQ_OK;
+}
+
+}  // namespace
+
+// One bundle iteration of (F)CG's operator part: t = D_oe p; q = m^2 p - D_eo t; <p, q>.
+int cg_apply_op(hisq_ctx *ctx, int op_prec, double mass, int n, const void *p, void *t, void *q,
+                double *partial, int *nblk, const int *active) {
+  RETCHK(launch_dslash(ctx, 1, op_prec, n, p, t, false, 0.0, nullptr, nullptr, nullptr, active));
+  RETCHK(launch_dslash(ctx, 0, op_prec, n, t, q, true, mass * mass, p, partial, nblk, active));
+  return HISQ_OK;
+}
+
+// Final bookkeeping shared by all solvers: FP64 true residual of every rhs, stats.
+int cg_finish(hisq_ctx *ctx, double mass, int n, const void *b, void *x, double tol, CGState *S,
+              CGState *hS, double *partial, hisq_cg_stats *st, bool *all_conv) {
+  const Geometry &g = ctx->g;
+  void *t64, *mx64;
+  RETCHK(ws_get(ctx, WS_CG5, size_t(n) * 3 * g.vh * 16, &mx64));
+  RETCHK(ws_get(ctx, WS_CG6, size_t(n) * 3 * g.vh * 16, &t64));
+  RETCHK(apply_m64(ctx, mass, n, x, t64, mx64, S->fin));
+  RETCHK(cg_replace_r(ctx, HISQ_F64, b, mx64, nullptr, nullptr, S, S->fin, n, partial));
+  RETCHK(cg_reduce_true(ctx, partial, S, n, tol * tol, 1));
+  RETCHK(poll(ctx, S, hS));
+  bool ok = true;
+  long long site_rhs = 0;
+  for (int i = 0; i < n; ++i) {
+    double res = hS->bnorm2[i] > 0 ? std::sqrt(hS->rr_true[i] / hS->bnorm2[i]) : std::sqrt(hS->rr_true[i]);
+    bool conv = std::isfinite(res) && res <= tol;
+    ok = ok && conv;
+    if (st) {
+      if (st->iters) st->iters[i] = hS->iters[i];
+      if (st->true_resid) st->true_resid[i] = res;
+      if (st->converged) st->converged[i] = conv ? 1 : 0;
+    }
+    site_rhs += 2LL * g.vh * (hS->iters[i] + hS->replacements[i]);
+  }
+  if (st) {
+    st->dslash_site_rhs = site_rhs;
+    st->peak_bytes = ws_total(ctx);
+  }
+  *all_conv = ok;
+  return HISQ_OK;
+}
+
+static int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
+                    const hisq_cg_params *prm, hisq_cg_stats *st, CGState *S, CGState *hS,
+                    double *partial) {
+  const Geometry &g = ctx->g;
+  const bool mixed = prm->kind == HISQ_CG_MIXED;
+  const int body = mixed ? HISQ_F32 : HISQ_F64;
+  int op_prec = mixed ? prm->link_prec : HISQ_F64;
+  const size_t vb = size_t(n) * 3 * g.vh * cplx_bytes(body);
+  const double tol2 = prm->tol * prm->tol;
+  const int check_every = prm->check_every > 0 ? prm->check_every : 8;
+  const int reliable_every = prm->reliable_every > 0 ? prm->reliable_every : 50;
+  Vecs v;
+  RETCHK(ws_get(ctx, WS_CG0, vb, &v.r));
+  RETCHK(ws_get(ctx, WS_CG1, vb, &v.p));
+  RETCHK(ws_get(ctx, WS_CG2, vb, &v.q));
+  RETCHK(ws_get(ctx, WS_CG3, vb, &v.t));
+  if (mixed) {
+    RETCHK(ws_get(ctx, WS_CG4, vb, &v.xh));
+    RETCHK(ws_get(ctx, WS_CG5, size_t(n) * 3 * g.vh * 16, &v.mx64));
+    RETCHK(ws_get(ctx, WS_CG6, size_t(n) * 3 * g.vh * 16, &v.t64));
+  }
+
+  // ---- initial residual ----
+  RETCHK(cg_init_state(ctx, b, S, n, partial));
+  RETCHK(cg_select(ctx, S, n, 1));
+  RETCHK(cg_zero(ctx, HISQ_F64, x, S->sel, 1, n));  // x = 0 where b = 0
+  if (prm->use_x0) {
+    void *mx = mixed ? v.mx64 : v.q;
+    void *tt = mixed ? v.t64 : v.t;
+    RETCHK(apply_m64(ctx, mass, n, x, tt, mx, S->sel));
+    RETCHK(cg_replace_r(ctx, body, b, mx, v.r, v.p, S, S->sel, n, partial));
+  } else {
+    RETCHK(cg_zero(ctx, HISQ_F64, x, nullptr, 0, n));
+    void *zero64 = mixed ? v.mx64 : v.q;
+    RETCHK(cg_zero(ctx, HISQ_F64, zero64, nullptr, 0, n));
+    RETCHK(cg_replace_r(ctx, body, b, zero64, v.r, v.p, S, S->sel, n, partial));
+  }
+  RETCHK(cg_set_rho(ctx, partial, S, n, tol2));
+  if (mixed) RETCHK(cg_zero(ctx, HISQ_F32, v.xh, nullptr, 0, n));
+  RETCHK(poll(ctx, S, hS));
+  for (int i = 0; i < n; ++i)
+    if (hS->status[i] == CG_NONFINITE)
+      return set_err(ctx, HISQ_ERR_NONFINITE, "hisq_cg_mrhs: non-finite source %d", i);
+
+  // host-side stagnation bookkeeping (mixed): best true residual and polls without progress
+  double best[HISQ_MAX_RHS];
+  int stale[HISQ_MAX_RHS];
+  int last_rep[HISQ_MAX_RHS];
+  for (int i = 0; i < n; ++i) {
+    best[i] = hS->rr_true[i];
+    stale[i] = 0;
+    last_rep[i] = 0;
+  }
+
+  auto reliable = [&](int all) -> int {
+    RETCHK(cg_select(ctx, S, n, all));
+    if (mixed) {
+      RETCHK(cg_accum_x(ctx, x, v.xh, S->sel, n));
+      RETCHK(apply_m64(ctx, mass, n, x, v.t64, v.mx64, S->sel));
+      RETCHK(cg_replace_r(ctx, body, b, v.mx64, v.r, nullptr, S, S->sel, n, partial));
+    } else {  // verify, restart from x if the true residual misses tol
+      RETCHK(apply_m64(ctx, mass, n, x, v.t, v.q, S->sel));
+      RETCHK(cg_replace_r(ctx, body, b, v.q, v.r, v.p, S, S->sel, n, partial));
+    }
+    RETCHK(cg_reduce_true(ctx, partial, S, n, tol2, 0));
+    return HISQ_OK;
+  };
+
+  int it = 0;
+  int nactive = 0;
+  for (int i = 0; i < n; ++i) nactive += hS->active[i];
+  int reps = 0;
+  while (nactive > 0 && it < prm->max_iter) {
+    int nblk_d = 0;
+    RETCHK(cg_apply_op(ctx, op_prec, mass, n, v.p, v.t, v.q, partial, &nblk_d, S->active));
+    RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, n));
+    RETCHK(cg_update_xr(ctx, body, !mixed, mixed ? v.xh : x, v.r, v.p, v.q, S, n, partial));
+    RETCHK(cg_reduce_beta(ctx, partial, S, n, tol2));
+    RETCHK(cg_update_p(ctx, body, v.r, v.p, S, n));
+    ++it;
+    if (mixed && it % reliable_every == 0) {
+      RETCHK(reliable(1));
+      ++reps;
+    }
+    if (it % check_every == 0 || it == prm->max_iter) {
+      RETCHK(poll(ctx, S, hS));
+      bool any_hit = false;
+      for (int i = 0; i < n; ++i) any_hit = any_hit || (hS->active[i] && hS->hit[i]);
+      if (any_hit) {
+        RETCHK(reliable(0));
+        ++reps;
+        RETCHK(poll(ctx, S, hS));
+      }
+      nactive = 0;
+      for (int i = 0; i < n; ++i) nactive += hS->active[i];
+      if (mixed) {
+        // Stagnation of the true residual with FP16 links: switch the inner operator to FP32
+        // links (the FP16 operator error ~5e-4 can stall the reliable updates).
+        for (int i = 0; i < n; ++i) {
+          if (!hS->active[i] || hS->replacements[i] == last_rep[i]) continue;
+          last_rep[i] = hS->replacements[i];
+          if (hS->rr_true[i] < 0.25 * best[i]) {
+            best[i] = hS->rr_true[i];
+            stale[i] = 0;
+          } else if (++stale[i] >= 6 && op_prec == HISQ_F16 && ctx->links[HISQ_F32].base) {
+            op_prec = HISQ_F32;
+            for (int k = 0; k < n; ++k) stale[k] = 0;
+          }
+        }
+      }
+    }
+  }
+  if (mixed) {  // fold the last FP32 correction of every rhs into x
+    RETCHK(cg_accum_x(ctx, x, v.xh, S->fin, n));
+  }
+  bool ok = false;
+  RETCHK(cg_finish(ctx, mass, n, b, x, prm->tol, S, hS, partial, st, &ok));
+  if (st) {
+    st->total_iters = it;
+    st->reliable_updates = reps;
+    if (st->fell_back)
+      for (int i = 0; i < n; ++i) st->fell_back[i] = 0;
+  }
+  if (!ok) return set_err(ctx, HISQ_ERR_NOCONV, "hisq_cg_mrhs: some rhs missed tol %.3g", prm->tol);
+  return HISQ_OK;
+}
+
+extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
+                            const hisq_cg_params *prm, hisq_cg_stats *st) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!b || !x || !prm) return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: null pointer");
+  if (b == x) return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: b and x alias");
+  if (n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: n = %d outside 1..%d", n, HISQ_MAX_RHS);
+  if (!(prm->tol > 0) || prm->max_iter < 1 || !std::isfinite(mass))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: need tol > 0, max_iter >= 1, finite mass");
+  if (prm->kind != HISQ_CG_F64 && prm->kind != HISQ_CG_MIXED && prm->kind != HISQ_FCG_NN)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: bad solver kind %d", prm->kind);
+  if (prm->kind != HISQ_CG_F64 && prm->link_prec != HISQ_F32 && prm->link_prec != HISQ_F16)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: link_prec must be HISQ_F32 or HISQ_F16");
+  if (!ctx->links_loaded) return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: no links loaded");
+  if (!ctx->links[HISQ_F64].base)
+    return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: the FP64 link copy is required");
+  if (prm->kind != HISQ_CG_F64 && !ctx->links[prm->link_prec].base)
+    return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: link copy of the requested precision missing");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  auto t0 = std::chrono::steady_clock::now();
+  void *sp, *pp, *hp;
+  RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));
+  const int nblk_max = std::max(blas_nblk(ctx), (ctx->g.vh + 255) / 256);
+  RETCHK(ws_get(ctx, WS_PARTIAL, size_t(n) * nblk_max * sizeof(double), &pp));
+  RETCHK(pinned_get(ctx, sizeof(CGState), &hp));
+  CGState *S = static_cast<CGState *>(sp);
+  CGState *hS = static_cast<CGState *>(hp);
+  double *partial = static_cast<double *>(pp);
+  int rc;
+  if (prm->kind == HISQ_FCG_NN)
+    rc = fcg_nn_solve(ctx, mass, n, b, x, prm, st, S, hS, partial);
+  else
+    rc = cg_solve(ctx, mass, n, b, x, prm, st, S, hS, partial);
+  if (st)
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
+}

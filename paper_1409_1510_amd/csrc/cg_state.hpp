@@ -1,0 +1,42 @@
+// Per-rhs device state of the multi-rhs CG solvers (one instance in device memory per solve,
+// mirrored to pinned host memory at the host's convergence polls).
+#pragma once
+
+#include "hisq.h"
+
+enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2, CG_NONFINITE = 3 };
+
+struct CGState {
+  double rho[HISQ_MAX_RHS];      // <r, r> of the iterated residual (or <z, r> for FCG)
+  double pq[HISQ_MAX_RHS];       // Re <p, M p>
+  double alpha[HISQ_MAX_RHS];
+  double beta[HISQ_MAX_RHS];
+  double bnorm2[HISQ_MAX_RHS];   // ||b||^2
+  double rr[HISQ_MAX_RHS];       // ||r||^2 of the iterated residual
+  double rr_true[HISQ_MAX_RHS];  // ||b - M x||^2 at the last FP64 recomputation
+  double aux[HISQ_MAX_RHS];      // FCG: <z, q>
+  int active[HISQ_MAX_RHS];      // 1 while the rhs iterates
+  int hit[HISQ_MAX_RHS];         // iterated residual below tol since the last true residual
+  int sel[HISQ_MAX_RHS];         // rhs selected for the current true-residual recomputation
+  int fin[HISQ_MAX_RHS];         // rhs included in the final residual report
+  int status[HISQ_MAX_RHS];      // CG_RUNNING / CG_CONVERGED / CG_BREAKDOWN / CG_NONFINITE
+  int iters[HISQ_MAX_RHS];
+  int replacements[HISQ_MAX_RHS];
+};
+
+// launchers in blas.hip
+struct hisq_ctx;
+int blas_nblk(const hisq_ctx *ctx);
+int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n);
+int cg_update_xr(hisq_ctx *ctx, int body_prec, bool x64, void *x, void *r, const void *p,
+                 const void *q, CGState *S, int n, double *partial);
+int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
+int cg_update_p(hisq_ctx *ctx, int body_prec, const void *r, void *p, const CGState *S, int n);
+int cg_select(hisq_ctx *ctx, CGState *S, int n, int all);
+int cg_accum_x(hisq_ctx *ctx, void *x64, void *xh32, const int *mask, int n);
+int cg_replace_r(hisq_ctx *ctx, int body_prec, const void *b, const void *mx, void *r, void *p,
+                 const CGState *S, const int *sel, int n, double *partial);
+int cg_reduce_true(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2, int final_only);
+int cg_init_state(hisq_ctx *ctx, const void *b, CGState *S, int n, double *partial);
+int cg_set_rho(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
+int cg_zero(hisq_ctx *ctx, int prec, void *v, const int *sel, int invert, int n);

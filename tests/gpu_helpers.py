@@ -1,0 +1,40 @@
+"""Shared helpers of the GPU parity tests (inputs from synth, expected values from oracle)."""
+import numpy as np
+
+import synth
+
+DEV = "cuda:0"
+
+
+def rel_elem(got, ref):
+    """max_i |got_i - ref_i| / max(|ref_i|, 1e-3 * rms(ref)): per-element relative error with a
+    floor for elements that cancel to ~0."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3 * rms)))
+
+
+def rel_l2(got, ref):
+    got = np.asarray(got, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+_LINK_CACHE = {}
+
+
+def links(dims, seed, eps=0.4):
+    key = (tuple(dims), seed, eps)
+    if key not in _LINK_CACHE:
+        _LINK_CACHE.clear()
+        _LINK_CACHE[key] = synth.gauge_links(dims, seed, eps=eps)
+    return _LINK_CACHE[key]
+
+
+def make_lattice(dims, seed, copies=7, recon=18, eps=0.4):
+    from paper_1409_1510_amd import hisq
+    fat, naik = links(dims, seed, eps)
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(fat, naik, copies, recon)
+    return lat, fat, naik

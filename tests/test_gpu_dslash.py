@@ -1,0 +1,199 @@
+"""GPU parity of the multi-rhs half Dslash, the M operator and the reductions against the oracle.
+
+Tolerances: FP64 per element 1e-13 relative (floor 1e-3 rms for elements that cancel), FP32
+relative L2 1e-6, FP32 arithmetic with FP16 link storage relative L2 2e-3 (binary16 rounds links
+to 4.9e-4 relative).  Multi-rhs output must be bit-identical to single-rhs calls.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import DEV, make_lattice, rel_elem, rel_l2
+
+torch = pytest.importorskip("torch")
+from paper_1409_1510_amd import hisq  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# (dims, n): extents 4 alias the +3/-1 hops; 6 aliases +3/-3; ragged V/2 (not a multiple of the
+# 256-site workgroup) and rhs counts that leave partial register tiles.
+CASES = [((4, 4, 4, 4), 1), ((6, 4, 4, 8), 3), ((8, 6, 4, 10), 5), ((8, 8, 8, 8), 16),
+         ((12, 4, 6, 8), 9)]
+
+
+def _vecs(dims, n, seed):
+    return synth.sources(dims, n, seed)
+
+
+@pytest.mark.parametrize("dims,n", CASES)
+@pytest.mark.parametrize("out_parity", [0, 1])
+def test_f64_matches_oracle(dims, n, out_parity):
+    lat, fat, naik = make_lattice(dims, 100)
+    v = _vecs(dims, n, 101)
+    got = lat.dslash(out_parity, hisq.HISQ_F64, torch.from_numpy(v).to(DEV)).cpu().numpy()
+    ref = oracle.dslash_half(fat, naik, v, dims, out_parity)
+    assert rel_elem(got, ref) <= 1e-13
+    lat.close()
+
+
+@pytest.mark.parametrize("dims,n", CASES)
+@pytest.mark.parametrize("recon", [18, 14])
+def test_f32_matches_oracle(dims, n, recon):
+    lat, fat, naik = make_lattice(dims, 102, recon=recon)
+    v = _vecs(dims, n, 103)
+    for par in (0, 1):
+        got = lat.dslash(par, hisq.HISQ_F32, torch.from_numpy(v).to(DEV).to(torch.complex64))
+        ref = oracle.dslash_half(fat, naik, v, dims, par)
+        err = rel_l2(got.cpu().numpy(), ref)
+        print(f"FP32 r{recon} dims={dims} n={n} parity={par}: rel L2 {err:.3g}")
+        assert err <= 1e-6
+    lat.close()
+
+
+@pytest.mark.parametrize("recon", [18, 14])
+def test_f16_links_matches_oracle(recon):
+    dims, n = (8, 6, 4, 10), 5
+    lat, fat, naik = make_lattice(dims, 104, recon=recon)
+    v = _vecs(dims, n, 105)
+    for par in (0, 1):
+        got = lat.dslash(par, hisq.HISQ_F16, torch.from_numpy(v).to(DEV).to(torch.complex64))
+        ref = oracle.dslash_half(fat, naik, v, dims, par)
+        err = rel_l2(got.cpu().numpy(), ref)
+        print(f"FP16 links r{recon} parity={par}: rel L2 {err:.3g}")
+        assert 1e-5 < err <= 2e-3  # above FP32 level: the links really are binary16
+    lat.close()
+
+
+@pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
+                                        (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 18),
+                                        (hisq.HISQ_F16, 14)])
+def test_multi_rhs_bit_identical_to_single(prec, recon):
+    dims = (8, 6, 4, 10)
+    lat, fat, naik = make_lattice(dims, 106, recon=recon)
+    dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
+    for n in (2, 7, 16, 23):
+        v = torch.from_numpy(_vecs(dims, n, 107 + n)).to(DEV).to(dt)
+        for par in (0, 1):
+            multi = lat.dslash(par, prec, v)
+            singles = torch.stack([lat.dslash(par, prec, v[i:i + 1].contiguous())[0] for i in range(n)])
+            assert torch.equal(multi.view(torch.float64 if dt == torch.complex128 else torch.float32),
+                               singles.view(torch.float64 if dt == torch.complex128 else torch.float32))
+    lat.close()
+
+
+def test_max_rhs_and_errors():
+    dims = (4, 4, 4, 6)
+    lat, fat, naik = make_lattice(dims, 108)
+    n = hisq.HISQ_MAX_RHS
+    v = _vecs(dims, n, 109)
+    got = lat.dslash(1, hisq.HISQ_F64, torch.from_numpy(v).to(DEV)).cpu().numpy()
+    ref = oracle.dslash_half(fat, naik, v, dims, 1)
+    assert rel_elem(got, ref) <= 1e-13
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, n + 1, torch.from_numpy(v).to(DEV),
+                              torch.from_numpy(v).to(DEV))
+    assert e.value.code == hisq.HISQ_ERR_ARG
+    x = torch.from_numpy(v[:1]).to(DEV)
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, 1, x, x)
+    assert e.value.code == hisq.HISQ_ERR_ARG
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_dslash_mrhs(lat.ctx, 2, hisq.HISQ_F64, 1, x, x.clone())
+    assert e.value.code == hisq.HISQ_ERR_ARG
+    lat.close()
+
+
+def test_state_and_link_errors():
+    dims = (4, 4, 4, 4)
+    lat = hisq.Lattice(dims, 0)
+    x = torch.zeros((1, 3, lat.vh), dtype=torch.complex128, device=DEV)
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, 1, x, x.clone())
+    assert e.value.code == hisq.HISQ_ERR_STATE
+    fat, naik = synth.gauge_links(dims, 110)
+    bad = fat.copy()
+    bad[3, 1, 2, 2] = np.nan
+    with pytest.raises(hisq.HisqError) as e:
+        lat.load_links(bad, naik)
+    assert e.value.code == hisq.HISQ_ERR_NONFINITE
+    with pytest.raises(hisq.HisqError) as e:  # fat links are not c * U(3): r14 must refuse
+        lat.load_links(naik, fat, naik_recon=14)
+    assert e.value.code == hisq.HISQ_ERR_ARG
+    # only the FP32 copy: FP64 calls fail cleanly
+    lat.load_links(fat, naik, copies=hisq.HISQ_LINKS_F32)
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, 1, x, x.clone())
+    assert e.value.code == hisq.HISQ_ERR_STATE
+    lat.close()
+
+
+def test_links_from_device_memory():
+    dims = (6, 4, 4, 8)
+    fat, naik = synth.gauge_links(dims, 111)
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(torch.from_numpy(fat).to(DEV), torch.from_numpy(naik).to(DEV))
+    v = _vecs(dims, 2, 112)
+    got = lat.dslash(0, hisq.HISQ_F64, torch.from_numpy(v).to(DEV)).cpu().numpy()
+    assert rel_elem(got, oracle.dslash_half(fat, naik, v, dims, 0)) <= 1e-13
+    lat.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(hisq.HISQ_F64, 1e-13), (hisq.HISQ_F32, 1e-6)])
+def test_apply_m_and_pq(prec, tol):
+    dims, n, mass = (8, 6, 4, 10), 6, 0.1
+    lat, fat, naik = make_lattice(dims, 113)
+    v = _vecs(dims, n, 114)
+    dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
+    out, pq = lat.apply_m(prec, mass, torch.from_numpy(v).to(DEV).to(dt), with_pq=True)
+    ref = oracle.m_ee(fat, naik, v, dims, mass)
+    got = out.cpu().numpy()
+    if prec == hisq.HISQ_F64:
+        assert rel_elem(got, ref) <= tol
+    else:
+        assert rel_l2(got, ref) <= tol
+    pq_ref = np.array([np.vdot(v[i], ref[i]).real for i in range(n)])
+    assert np.max(np.abs(pq.cpu().numpy() - pq_ref) / pq_ref) <= (1e-12 if prec == hisq.HISQ_F64 else 1e-6)
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [hisq.HISQ_F64, hisq.HISQ_F32])
+def test_dot(prec):
+    dims, n = (8, 6, 4, 10), 5
+    lat = hisq.Lattice(dims, 0)
+    a = _vecs(dims, n, 115)
+    b = _vecs(dims, n, 116)
+    dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
+    ta, tb = torch.from_numpy(a).to(DEV).to(dt), torch.from_numpy(b).to(DEV).to(dt)
+    got = lat.dot(prec, ta, tb).cpu().numpy()
+    a2, b2 = ta.cpu().numpy().astype(np.complex128), tb.cpu().numpy().astype(np.complex128)
+    ref = np.array([np.vdot(a2[i], b2[i]) for i in range(n)])
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # deterministic: same bits on a second call
+    assert np.array_equal(got, lat.dot(prec, ta, tb).cpu().numpy())
+    lat.close()
+
+
+def test_full_size_32c8_sampled_sites():
+    """The workload lattice 32^3 x 8 with 16 rhs, FP64 and FP32, in the benchmarked launch
+    configuration: sampled output sites against the per-site oracle, plus the exact identity
+    <a, D_oe b> = -<D_eo a, b> over the whole lattice."""
+    cfg = synth.WORKLOADS["c1"]
+    dims, n = cfg["dims"], 16
+    lat, fat, naik = make_lattice(dims, synth.workload_seed("c1"))
+    v = synth.sources(dims, n, synth.workload_seed("c1") + 1)
+    rng = np.random.default_rng(5)
+    sites = np.concatenate([[0, 1, lat.vh - 1], rng.choice(lat.vh, 40, replace=False)])
+    tv = torch.from_numpy(v).to(DEV)
+    for par in (0, 1):
+        ref = oracle.dslash_sites(fat, naik, v, dims, par, sites)
+        got64 = lat.dslash(par, hisq.HISQ_F64, tv).cpu().numpy()[:, :, sites]
+        assert rel_elem(got64, ref) <= 1e-13
+        got32 = lat.dslash(par, hisq.HISQ_F32, tv.to(torch.complex64)).cpu().numpy()[:, :, sites]
+        assert rel_l2(got32, ref) <= 1e-6
+    a = torch.from_numpy(synth.sources(dims, n, 7)).to(DEV)
+    b = torch.from_numpy(synth.sources(dims, n, 8)).to(DEV)
+    lhs = lat.dot(hisq.HISQ_F64, lat.dslash(1, hisq.HISQ_F64, a), b)   # <D_oe a, b>  (odd)
+    rhs = lat.dot(hisq.HISQ_F64, a, lat.dslash(0, hisq.HISQ_F64, b))   # <a, D_eo b>  (even)
+    assert torch.max(torch.abs(lhs + rhs)) <= 1e-10 * torch.max(torch.abs(lhs))
+    lat.close()

@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
+                         "kernel (counter calibration), then --steps FP32 Dslash steps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver works on a single device (the multi-GPU "
@@ -92,6 +95,19 @@ def main():
     v_o = torch.from_numpy(synth.sources(dims, n, seed + 2)).to("cuda:0").to(torch.complex64)
     w_e = torch.empty_like(v_e)
     w_o = torch.empty_like(v_o)
+
+    if args.profile:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            lat.dslash(1, hisq.HISQ_F32, v_e, w_o)
+            lat.dslash(0, hisq.HISQ_F32, v_o, w_e)
+        torch.cuda.synchronize()
+        print(f"profile run done: {args.steps} steps, {n} rhs, lattice {dims}")
+        lat.close()
+        return
 
     ms_step, ms_launch = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
                                             args.steps, args.warmup)

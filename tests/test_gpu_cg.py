@@ -43,9 +43,10 @@ def test_dense_lu_4444():
     lat, fat, naik = make_lattice(dims, 200)
     b = synth.sources(dims, 3, 201)
     x, info = _solve(lat, mass, b, kind=hisq.HISQ_CG_F64, tol=1e-12)
-    # reference: M assembled densely from the oracle M applied to unit vectors
+    # reference: M as a dense matrix, column j = oracle M applied to unit vector j (vectors
+    # flattened in their [3][V/2] order), solved by LAPACK
     vh = lat.vh
-    eye = np.eye(3 * vh).reshape(3 * vh, vh, 3).transpose(0, 2, 1)
+    eye = np.eye(3 * vh).reshape(3 * vh, 3, vh)
     cols = oracle.m_ee(fat, naik, eye, dims, mass).reshape(3 * vh, 3 * vh).T
     for i in range(3):
         x_lu = np.linalg.solve(cols, b[i].ravel()).reshape(3, vh)

@@ -115,6 +115,30 @@ int hisq_apply_m(hisq_ctx *ctx, int prec, double mass, int n, const void *in, vo
  * (re, im).  Asynchronous. */
 int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, const void *b, double *dots);
 
+/* Launch configuration of the multi-rhs half Dslash.  Section 2 blocks the rhs in registers,
+ * blocks sites x rhs in 2-d thread blocks, combines both, and picks the best launch
+ * configuration for the GPU, the lattice size and n by automatic tuning.  The library does the
+ * same: each (precision, n, plain or fused-M form) is tuned on first use (a few ms of scratch
+ * launches) unless the environment sets HISQ_AUTOTUNE=0 (then a fixed heuristic is used) or a
+ * configuration is forced.  Every configuration gives bit-identical Dslash output. */
+typedef struct {
+  int rhs_per_thread;    /* register tile: 1, 2, 4, 8 or 16 (FP64 and the fused-M form: <= 8)  */
+  int sites_per_block;   /* 256: one rhs tile per 256-thread workgroup; 64: the 4 waves of a     */
+                         /*      workgroup take 4 rhs tiles of the same 64 sites               */
+  int nontemporal_links; /* 1: link loads carry the non-temporal cache hint                     */
+} hisq_launch;
+
+/* Force the configuration for (prec, n), both forms (the fused-M form clamps rhs_per_thread to
+ * its limit); cfg = NULL restores automatic tuning.  HISQ_ERR_ARG for an invalid configuration. */
+int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch *cfg);
+
+/* The configuration the next call with (prec, n, fused_m) uses (the heuristic if not tuned yet). */
+int hisq_get_launch(hisq_ctx *ctx, int prec, int n, int fused_m, hisq_launch *cfg);
+
+/* Tune (prec, n, fused_m) now: time every valid configuration on scratch vectors and keep the
+ * fastest.  best and ms_out (mean ms per launch) may be NULL.  Synchronises the stream. */
+int hisq_autotune(hisq_ctx *ctx, int prec, int n, int fused_m, hisq_launch *best, double *ms_out);
+
 typedef struct {
   int kind;           /* HISQ_CG_F64, HISQ_CG_MIXED or HISQ_FCG_NN                              */
   double tol;         /* stop rhs i when ||b_i - M x_i|| / ||b_i|| <= tol, checked in FP64         */

@@ -237,7 +237,7 @@ extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, vo
   auto t0 = std::chrono::steady_clock::now();
   void *sp, *pp, *hp;
   RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));
-  const int nblk_max = std::max(blas_nblk(ctx), (ctx->g.vh + 255) / 256);
+  const int nblk_max = std::max(blas_nblk(ctx), dslash_partials(ctx->g));
   RETCHK(ws_get(ctx, WS_PARTIAL, size_t(n) * nblk_max * sizeof(double), &pp));
   RETCHK(pinned_get(ctx, sizeof(CGState), &hp));
   CGState *S = static_cast<CGState *>(sp);

@@ -1,295 +1,209 @@
-// Multi-rhs HISQ half Dslash for gfx950 (Section 1, Eq. 3 and Eq. 4).
-//
-// One thread owns one output site and a tile of RT right-hand sides (register blocking over
-// rhs, Section 2): every link of the site is loaded once per tile and applied to the RT
-// neighbour vectors, and tiles of the same sites run in neighbouring workgroups of the same XCD
-// so that a second tile finds the links in that XCD's L2 (the 2-d site x rhs blocking of
-// Section 2).  Hops are accumulated in a fixed order with explicit FMAs, so the result for a
-// right-hand side does not depend on n or on the tile it is computed in.
-//
-// Layouts: links as packed by links.hip (planes of V/2 complex per matrix entry, per output
-// parity); vectors [n][3][V/2] complex (colour-planar structure of arrays, Section 2).
-#include "internal.hpp"
+// Multi-rhs HISQ half Dslash: launch-configuration choice (automatic tuning, Section 2), the
+// C ABI entry points hisq_dslash_mrhs / hisq_apply_m and the tuning controls.  The kernel
+// itself is in dslash_kernel.hpp, instantiated per precision in dslash_f64/f32/f16.hip.
+#include "dslash_kernel.hpp"
 
 #include <cstdlib>
 
+using dslash::Args;
+using dslash::DslashFn;
+
 namespace {
 
-template <typename Real> struct CT;
-template <> struct CT<double> { using T = double2; };
-template <> struct CT<float> { using T = float2; };
-
-__device__ inline void ld_link(const double2 *p, double &re, double &im) {
-  double2 v = *p;
-  re = v.x;
-  im = v.y;
-}
-__device__ inline void ld_link(const float2 *p, float &re, float &im) {
-  float2 v = *p;
-  re = v.x;
-  im = v.y;
-}
-__device__ inline void ld_link(const __half2 *p, float &re, float &im) {
-  float2 v = __half22float2(*p);
-  re = v.x;
-  im = v.y;
+DslashFn lookup(int prec, int recon, bool epi, const hisq_launch &c) {
+  if (prec == HISQ_F64) return dslash_fn_f64(epi, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links);
+  if (prec == HISQ_F32)
+    return dslash_fn_f32(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links);
+  return dslash_fn_f16(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links);
 }
 
-__device__ inline double fmaR(double a, double b, double c) { return fma(a, b, c); }
-__device__ inline float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+bool config_valid(int prec, bool epi, const hisq_launch &c) {
+  const int rt = c.rhs_per_thread;
+  if (rt != 1 && rt != 2 && rt != 4 && rt != 8 && rt != 16) return false;
+  if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
+  if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
+  return lookup(prec, 18, epi, c) != nullptr;
+}
 
-template <typename Real> struct Lnk {
-  Real re[3][3], im[3][3];
+int next_pow2(int n) {
+  int p = 1;
+  while (p < n) p *= 2;
+  return p;
+}
+
+// Heuristic used until a configuration is tuned or forced.
+hisq_launch heuristic(int prec, int n, bool epi) {
+  int cap = (prec == HISQ_F64 || epi) ? 4 : 8;
+  int rt = 1;
+  while (rt * 2 <= cap && rt * 2 <= n) rt *= 2;
+  return hisq_launch{rt, 256, 0};
+}
+
+struct Geo {
+  int ntiles, ngroups, nsblk, grid;
 };
 
-// Load the link of hop k at site s; a 14-real Naik link gets row 2 = z * conj(row0 x row1).
-template <typename Real, typename LT, bool R14>
-__device__ inline void load_link(const LT *__restrict__ links, int plane, unsigned vh, unsigned s,
-                                 Lnk<Real> &L) {
-  const LT *p = links + size_t(plane) * vh + s;
-  constexpr int rows = R14 ? 2 : 3;
-#pragma unroll
-  for (int a = 0; a < rows; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) ld_link(p + (a * 3 + b) * vh, L.re[a][b], L.im[a][b]);
-  if constexpr (R14) {
-    Real zr, zi;
-    ld_link(p + 6 * vh, zr, zi);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
-      // cross_b = r0[b1] r1[b2] - r0[b2] r1[b1]
-      Real cr = (L.re[0][b1] * L.re[1][b2] - L.im[0][b1] * L.im[1][b2]) -
-                (L.re[0][b2] * L.re[1][b1] - L.im[0][b2] * L.im[1][b1]);
-      Real ci = (L.re[0][b1] * L.im[1][b2] + L.im[0][b1] * L.re[1][b2]) -
-                (L.re[0][b2] * L.im[1][b1] + L.im[0][b2] * L.re[1][b1]);
-      // row2_b = z * conj(cross_b)
-      L.re[2][b] = zr * cr + zi * ci;
-      L.im[2][b] = zi * cr - zr * ci;
-    }
-  }
+Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
+  Geo o;
+  o.ntiles = (n + c.rhs_per_thread - 1) / c.rhs_per_thread;
+  const int tpb = 256 / c.sites_per_block;
+  o.ngroups = (o.ntiles + tpb - 1) / tpb;
+  o.nsblk = (g.vh + c.sites_per_block - 1) / c.sites_per_block;
+  const int nb = o.nsblk * o.ngroups;
+  o.grid = (nb + 7) / 8 * 8;
+  return o;
 }
 
-// acc += s * L v for RT right-hand sides (s = +1 forward hop, -1 backward hop).
-template <typename Real, int RT, bool NEG>
-__device__ inline void apply_hop(const Lnk<Real> &L, const typename CT<Real>::T *__restrict__ in,
-                                 unsigned vh, unsigned nbr, const bool *act,
-                                 Real (&acc_re)[RT][3], Real (&acc_im)[RT][3]) {
-  using C = typename CT<Real>::T;
-#pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    if (!act[r]) continue;
-    C v[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) v[b] = in[(unsigned)(r * 3 + b) * vh + nbr];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const Real lr = NEG ? -L.re[a][b] : L.re[a][b];
-        const Real li = NEG ? -L.im[a][b] : L.im[a][b];
-        acc_re[r][a] = fmaR(lr, v[b].x, acc_re[r][a]);
-        acc_re[r][a] = fmaR(-li, v[b].y, acc_re[r][a]);
-        acc_im[r][a] = fmaR(lr, v[b].y, acc_im[r][a]);
-        acc_im[r][a] = fmaR(li, v[b].x, acc_im[r][a]);
-      }
-    }
-  }
+int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *out, bool epi,
+        double mass2, const void *pvec, double *partial, const int *active, const hisq_launch &c) {
+  const LinkCopy &l = ctx->links[prec];
+  DslashFn fn = lookup(prec, l.recon, epi, c);
+  if (!fn) return set_err(ctx, HISQ_ERR_ARG, "invalid Dslash launch configuration");
+  const Geo geo = geometry(ctx->g, n, c);
+  Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
+         mass2, pvec, partial, active};
+  fn(a, dim3(geo.grid), ctx->stream);
+  LAUNCHCHK(ctx, "k_dslash");
+  return HISQ_OK;
 }
 
-template <typename Real, typename LT, int RT, bool R14, bool EPI>
-__global__ void __launch_bounds__(256)
-k_dslash(const LT *__restrict__ links, const typename CT<Real>::T *__restrict__ in_all,
-         typename CT<Real>::T *__restrict__ out_all, Geometry g, int out_parity, int n, int ntiles,
-         int nblk_sites, Real mass2, const typename CT<Real>::T *__restrict__ p_all,
-         double *__restrict__ partial, const int *__restrict__ active) {
-  using C = typename CT<Real>::T;
-  // XCD-aware order: hardware deals workgroups round-robin to the 8 XCDs; give each XCD a
-  // contiguous range of (site block, rhs tile) pairs so neighbour vectors and the links shared
-  // by the rhs tiles of a site block stay in one L2.
-  const int nb = nblk_sites * ntiles;
-  const int chunk = gridDim.x >> 3;
-  const int lb = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
-  if (lb >= nb) return;  // uniform for the whole workgroup
-  const int sblk = lb / ntiles;
-  const int tile = lb - sblk * ntiles;
-  const int r0 = tile * RT;
-  const unsigned vh = g.vh;
-  const unsigned s = sblk * 256 + threadIdx.x;
-  const bool valid = s < vh;
-  const size_t tile_off = size_t(r0) * 3 * vh;
-  const C *__restrict__ in = in_all + tile_off;
-  C *__restrict__ out = out_all + tile_off;
-
-  bool act[RT];
-#pragma unroll
-  for (int r = 0; r < RT; ++r) act[r] = (r0 + r < n) && (!active || active[r0 + r]);
-
-  Real acc_re[RT][3], acc_im[RT][3];
-#pragma unroll
-  for (int r = 0; r < RT; ++r)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) acc_re[r][a] = acc_im[r][a] = Real(0);
-
-  if (valid) {
-    const int xh = s % g.lxh;
-    int rest = s / g.lxh;
-    const int y = rest % g.ly;
-    rest /= g.ly;
-    const int z = rest % g.lz;
-    const int t = rest / g.lz;
-    const int x = 2 * xh + ((y + z + t + out_parity) & 1);
-    const unsigned rowbase = s - xh;
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-      unsigned f1, b1, f3, b3;
-      if (mu == 0) {
-        int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
-        int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
-        int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
-        int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
-        f1 = rowbase + (xf1 >> 1);
-        b1 = rowbase + (xb1 >> 1);
-        f3 = rowbase + (xf3 >> 1);
-        b3 = rowbase + (xb3 >> 1);
-      } else {
-        const int c = mu == 1 ? y : (mu == 2 ? z : t);
-        const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
-        const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
-        f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
-        b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
-        f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
-        b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
-      }
-      Lnk<Real> L;
-      load_link<Real, LT, false>(links, link_plane(mu, R14 ? 14 : 18), vh, s, L);
-      apply_hop<Real, RT, false>(L, in, vh, f1, act, acc_re, acc_im);
-      load_link<Real, LT, false>(links, link_plane(4 + mu, R14 ? 14 : 18), vh, s, L);
-      apply_hop<Real, RT, true>(L, in, vh, b1, act, acc_re, acc_im);
-      load_link<Real, LT, R14>(links, link_plane(8 + mu, R14 ? 14 : 18), vh, s, L);
-      apply_hop<Real, RT, false>(L, in, vh, f3, act, acc_re, acc_im);
-      load_link<Real, LT, R14>(links, link_plane(12 + mu, R14 ? 14 : 18), vh, s, L);
-      apply_hop<Real, RT, true>(L, in, vh, b3, act, acc_re, acc_im);
-    }
-  }
-
-  if constexpr (!EPI) {
-    if (valid) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        if (!act[r]) continue;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          C o;
-          o.x = acc_re[r][a];
-          o.y = acc_im[r][a];
-          out[(unsigned)(r * 3 + a) * vh + s] = o;
-        }
-      }
-    }
-  } else {
-    // q = m^2 p - D_eo t and the per-rhs FP64 partials of Re<p, q>
-    const C *__restrict__ pv = p_all + tile_off;
-    double dot[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      dot[r] = 0.0;
-      if (!act[r] || !valid) continue;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const C p = pv[(unsigned)(r * 3 + a) * vh + s];
-        C o;
-        o.x = fmaR(mass2, p.x, -acc_re[r][a]);
-        o.y = fmaR(mass2, p.y, -acc_im[r][a]);
-        out[(unsigned)(r * 3 + a) * vh + s] = o;
-        dot[r] = fma(double(p.x), double(o.x), dot[r]);
-        dot[r] = fma(double(p.y), double(o.y), dot[r]);
-      }
-    }
-    if (partial) {
-      __shared__ double red[RT][4];
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        double v = dot[r];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[r][wave] = v;
-      }
-      __syncthreads();
-      if ((int)threadIdx.x < RT && r0 + (int)threadIdx.x < n) {
-        const int r = threadIdx.x;
-        partial[size_t(r0 + r) * nblk_sites + sblk] = ((red[r][0] + red[r][1]) + red[r][2]) + red[r][3];
-      }
-    }
-  }
-}
-
-using DslashFn = void (*)(const void *, const void *, void *, Geometry, int, int, int, int, double,
-                          const void *, double *, const int *, dim3, hipStream_t);
-
-template <typename Real, typename LT, int RT, bool R14, bool EPI>
-void launch_t(const void *links, const void *in, void *out, Geometry g, int out_parity, int n,
-              int ntiles, int nblk_sites, double mass2, const void *p, double *partial,
-              const int *active, dim3 grid, hipStream_t st) {
-  using C = typename CT<Real>::T;
-  k_dslash<Real, LT, RT, R14, EPI><<<grid, 256, 0, st>>>(
-      static_cast<const LT *>(links), static_cast<const C *>(in), static_cast<C *>(out), g,
-      out_parity, n, ntiles, nblk_sites, Real(mass2), static_cast<const C *>(p), partial, active);
-}
-
-template <typename Real, typename LT, bool R14, bool EPI> DslashFn pick_rt(int rt) {
-  switch (rt) {
-    case 1: return launch_t<Real, LT, 1, R14, EPI>;
-    case 2: return launch_t<Real, LT, 2, R14, EPI>;
-    case 4: return launch_t<Real, LT, 4, R14, EPI>;
-    case 8: return launch_t<Real, LT, 8, R14, EPI>;
-    default: return launch_t<Real, LT, 16, R14, EPI>;
-  }
-}
-
-template <bool EPI> DslashFn pick(int prec, int recon, int rt) {
-  if (prec == HISQ_F64) return pick_rt<double, double2, false, EPI>(rt);
-  if (prec == HISQ_F32)
-    return recon == 14 ? pick_rt<float, float2, true, EPI>(rt) : pick_rt<float, float2, false, EPI>(rt);
-  return recon == 14 ? pick_rt<float, __half2, true, EPI>(rt) : pick_rt<float, __half2, false, EPI>(rt);
-}
-
-// Right-hand sides per thread.  Register budget (gfx950, 256-thread workgroups): FP64 tiles
-// above 8 and epilogue tiles above 8 spill, so those are capped.
-int default_rt(int prec, int n, bool epi) {
-  static int forced = [] {
-    const char *e = getenv("HISQ_DSLASH_RT");
-    return e ? atoi(e) : 0;
+bool autotune_enabled() {
+  static int on = [] {
+    const char *e = getenv("HISQ_AUTOTUNE");
+    return e ? atoi(e) : 1;
   }();
-  int cap = forced > 0 ? forced : (prec == HISQ_F64 ? 4 : 8);
-  if (prec == HISQ_F64 || epi) cap = cap > 8 ? 8 : cap;
-  int rt = 1;
-  while (rt * 2 <= cap && rt * 2 <= n && rt < 16) rt *= 2;
-  return rt;
+  return on != 0;
 }
 
 }  // namespace
 
+int dslash_partials(const Geometry &g) { return (g.vh + 63) / 64; }
+
+int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double *ms_out) {
+  const Geometry &g = ctx->g;
+  const size_t bytes = size_t(n) * 3 * g.vh * cplx_bytes(prec);
+  void *a, *b, *pp;
+  RETCHK(ws_get(ctx, WS_TUNE0, bytes, &a));
+  RETCHK(ws_get(ctx, WS_TUNE1, bytes, &b));
+  RETCHK(ws_get(ctx, WS_TUNE2, size_t(n) * dslash_partials(g) * sizeof(double), &pp));
+  HIPCHK(ctx, hipMemsetAsync(a, 0, bytes, ctx->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  hisq_launch best = heuristic(prec, n, epi);
+  float best_ms = 1e30f;
+  const int rts[] = {1, 2, 4, 8, 16};
+  int rc = HISQ_OK;
+  for (int rt : rts) {
+    if (rt > next_pow2(n)) break;
+    for (int spb : {256, 64})
+      for (int nt : {0, 1}) {
+        hisq_launch c{rt, spb, nt};
+        if (!config_valid(prec, epi, c)) continue;
+        const int reps = 3;
+        for (int k = 0; k <= reps && rc == HISQ_OK; ++k) {
+          if (k == 1) (void)hipEventRecord(e0, ctx->stream);
+          rc = run(ctx, epi ? 0 : 1, prec, n, a, b, epi, 0.01, a, static_cast<double *>(pp),
+                   nullptr, c);
+        }
+        if (rc != HISQ_OK) break;
+        (void)hipEventRecord(e1, ctx->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int slot : {WS_TUNE0, WS_TUNE1, WS_TUNE2}) {  // tuning scratch is not kept
+    (void)hipFree(ctx->ws[slot]);
+    ctx->ws[slot] = nullptr;
+    ctx->ws_bytes[slot] = 0;
+  }
+  if (rc != HISQ_OK) return rc;
+  TuneEntry &t = ctx->tune[prec][n][epi ? 1 : 0];
+  t.cfg = best;
+  t.state = TuneEntry::TUNED;
+  t.ms = best_ms;
+  if (best_out) *best_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return HISQ_OK;
+}
+
+int config_for(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *c) {
+  TuneEntry &t = ctx->tune[prec][n][epi ? 1 : 0];
+  if (t.state == TuneEntry::NONE) {
+    if (autotune_enabled()) {
+      RETCHK(tune(ctx, prec, n, epi, nullptr, nullptr));
+    } else {
+      t.cfg = heuristic(prec, n, epi);
+      t.state = TuneEntry::HEURISTIC;
+    }
+  }
+  *c = t.cfg;
+  return HISQ_OK;
+}
+
 int launch_dslash(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *out,
                   bool epi, double mass2, const void *pvec, double *partial, int *nblk_out,
                   const int *active) {
-  const Geometry &g = ctx->g;
-  const LinkCopy &l = ctx->links[prec];
-  if (!l.base)
+  if (!ctx->links[prec].base)
     return set_err(ctx, HISQ_ERR_STATE, "no %s link copy loaded (see hisq_load_links copies)",
                    prec == HISQ_F64 ? "FP64" : (prec == HISQ_F32 ? "FP32" : "FP16"));
-  const int rt = default_rt(prec, n, epi);
-  const int ntiles = (n + rt - 1) / rt;
-  const int nblk_sites = (g.vh + 255) / 256;
-  const int nb = nblk_sites * ntiles;
-  const int grid = (nb + 7) / 8 * 8;
-  DslashFn fn = epi ? pick<true>(prec, l.recon, rt) : pick<false>(prec, l.recon, rt);
-  fn(l.par[out_parity], in, out, g, out_parity, n, ntiles, nblk_sites, mass2, pvec, partial, active,
-     dim3(grid), ctx->stream);
-  LAUNCHCHK(ctx, "k_dslash");
-  if (nblk_out) *nblk_out = nblk_sites;
+  hisq_launch c;
+  RETCHK(config_for(ctx, prec, n, epi, &c));
+  RETCHK(run(ctx, out_parity, prec, n, in, out, epi, mass2, pvec, partial, active, c));
+  if (nblk_out) *nblk_out = dslash_partials(ctx->g);
   return HISQ_OK;
+}
+
+extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch *cfg) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!prec_valid(prec) || n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: bad precision or n");
+  for (int epi = 0; epi < 2; ++epi) {
+    TuneEntry &t = ctx->tune[prec][n][epi];
+    if (!cfg) {
+      t = TuneEntry{};
+      continue;
+    }
+    hisq_launch c = *cfg;
+    if (!config_valid(prec, epi, c)) {
+      if (epi) {  // the fused-M form caps the register tile: use the largest valid one
+        while (c.rhs_per_thread > 1 && !config_valid(prec, true, c)) c.rhs_per_thread /= 2;
+      }
+      if (!config_valid(prec, epi, c))
+        return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: invalid configuration (rt %d, spb %d, nt %d)",
+                       cfg->rhs_per_thread, cfg->sites_per_block, cfg->nontemporal_links);
+    }
+    t.cfg = c;
+    t.state = TuneEntry::FORCED;
+  }
+  return HISQ_OK;
+}
+
+extern "C" int hisq_get_launch(hisq_ctx *ctx, int prec, int n, int fused_m, hisq_launch *cfg) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!cfg || !prec_valid(prec) || n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_get_launch: bad argument");
+  const TuneEntry &t = ctx->tune[prec][n][fused_m ? 1 : 0];
+  *cfg = t.state == TuneEntry::NONE ? heuristic(prec, n, fused_m != 0) : t.cfg;
+  return HISQ_OK;
+}
+
+extern "C" int hisq_autotune(hisq_ctx *ctx, int prec, int n, int fused_m, hisq_launch *best,
+                             double *ms_out) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!prec_valid(prec) || n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_autotune: bad precision or n");
+  if (!ctx->links_loaded || !ctx->links[prec].base)
+    return set_err(ctx, HISQ_ERR_STATE, "hisq_autotune: link copy of this precision not loaded");
+  return tune(ctx, prec, n, fused_m != 0, best, ms_out);
 }
 
 extern "C" int hisq_dslash_mrhs(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in,
@@ -318,7 +232,7 @@ extern "C" int hisq_apply_m(hisq_ctx *ctx, int prec, double mass, int n, const v
   const Geometry &g = ctx->g;
   void *tmp;
   RETCHK(ws_get(ctx, WS_TMP_ODD, size_t(n) * 3 * g.vh * cplx_bytes(prec), &tmp));
-  const int nblk = (g.vh + 255) / 256;
+  const int nblk = dslash_partials(g);
   double *partial = nullptr;
   if (pq_out) {
     void *pp;

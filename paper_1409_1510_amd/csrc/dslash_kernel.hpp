@@ -1,0 +1,304 @@
+// Multi-rhs HISQ half Dslash kernel template for gfx950 (Section 1, Eq. 3 and Eq. 4).
+//
+// One thread owns one output site and a tile of RT right-hand sides (register blocking over rhs,
+// Section 2): each link of the site is loaded once per tile and applied to RT neighbour vectors.
+// Several tiles of the same sites are kept close together, either as the 4 waves of one
+// workgroup (SPB = 64 sites per workgroup: the waves read the same links through the CU's L1 --
+// the 2-d site x rhs blocking of Section 2) or as neighbouring workgroups on one XCD (SPB = 256:
+// the links are found in that XCD's L2).  Workgroups are remapped so that each XCD owns a
+// contiguous range of site blocks.  Hops are accumulated in a fixed order with explicit FMAs, so
+// the result for a rhs does not depend on n, on RT or on the workgroup shape.  Which shape is
+// fastest depends on the GPU, the lattice and n; the launcher picks it by timing (Section 2,
+// automatic tuning of the launch configuration).
+//
+// Layouts: links as packed by links.hip (planes of V/2 complex per matrix entry, per output
+// parity); vectors [n][3][V/2] complex (colour-planar structure of arrays).
+#pragma once
+
+#include "internal.hpp"
+
+namespace dslash {
+
+template <typename Real> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+template <bool NT> __device__ inline void ld_link(const double2 *p, double &re, double &im) {
+  if constexpr (NT) {
+    d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    re = v.x;
+    im = v.y;
+  } else {
+    double2 v = *p;
+    re = v.x;
+    im = v.y;
+  }
+}
+template <bool NT> __device__ inline void ld_link(const float2 *p, float &re, float &im) {
+  if constexpr (NT) {
+    f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+    re = v.x;
+    im = v.y;
+  } else {
+    float2 v = *p;
+    re = v.x;
+    im = v.y;
+  }
+}
+template <bool NT> __device__ inline void ld_link(const __half2 *p, float &re, float &im) {
+  __half2 h;
+  if constexpr (NT) {
+    unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(p));
+    h = *reinterpret_cast<__half2 *>(&u);
+  } else {
+    h = *p;
+  }
+  float2 v = __half22float2(h);
+  re = v.x;
+  im = v.y;
+}
+
+__device__ inline double fmaR(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float fmaR(float a, float b, float c) { return fmaf(a, b, c); }
+
+template <typename Real> struct Lnk {
+  Real re[3][3], im[3][3];
+};
+
+// Load the link of a hop at site s; a 14-real Naik link gets row 2 = z * conj(row0 x row1).
+template <typename Real, typename LT, bool R14, bool NT>
+__device__ inline void load_link(const LT *__restrict__ links, int plane, unsigned vh, unsigned s,
+                                 Lnk<Real> &L) {
+  const LT *p = links + size_t(plane) * vh + s;
+  constexpr int rows = R14 ? 2 : 3;
+#pragma unroll
+  for (int a = 0; a < rows; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) ld_link<NT>(p + (a * 3 + b) * vh, L.re[a][b], L.im[a][b]);
+  if constexpr (R14) {
+    Real zr, zi;
+    ld_link<NT>(p + 6 * vh, zr, zi);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+      // cross_b = r0[b1] r1[b2] - r0[b2] r1[b1]
+      Real cr = (L.re[0][b1] * L.re[1][b2] - L.im[0][b1] * L.im[1][b2]) -
+                (L.re[0][b2] * L.re[1][b1] - L.im[0][b2] * L.im[1][b1]);
+      Real ci = (L.re[0][b1] * L.im[1][b2] + L.im[0][b1] * L.re[1][b2]) -
+                (L.re[0][b2] * L.im[1][b1] + L.im[0][b2] * L.re[1][b1]);
+      // row2_b = z * conj(cross_b)
+      L.re[2][b] = zr * cr + zi * ci;
+      L.im[2][b] = zi * cr - zr * ci;
+    }
+  }
+}
+
+// acc += sign * L v for the RT right-hand sides of the tile (sign -1 for backward hops).
+template <typename Real, int RT, bool NEG>
+__device__ inline void apply_hop(const Lnk<Real> &L, const typename CT<Real>::T *__restrict__ in,
+                                 unsigned vh, unsigned nbr, const bool *act,
+                                 Real (&acc_re)[RT][3], Real (&acc_im)[RT][3]) {
+  using C = typename CT<Real>::T;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    if (!act[r]) continue;
+    C v[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) v[b] = in[(unsigned)(r * 3 + b) * vh + nbr];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const Real lr = NEG ? -L.re[a][b] : L.re[a][b];
+        const Real li = NEG ? -L.im[a][b] : L.im[a][b];
+        acc_re[r][a] = fmaR(lr, v[b].x, acc_re[r][a]);
+        acc_re[r][a] = fmaR(-li, v[b].y, acc_re[r][a]);
+        acc_im[r][a] = fmaR(lr, v[b].y, acc_im[r][a]);
+        acc_im[r][a] = fmaR(li, v[b].x, acc_im[r][a]);
+      }
+    }
+  }
+}
+
+struct Args {
+  const void *links;
+  const void *in;
+  void *out;
+  Geometry g;
+  int out_parity;
+  int n;
+  int ntiles;   // ceil(n / RT)
+  int ngroups;  // tile groups per site block
+  int nsblk;    // site blocks
+  double mass2;
+  const void *pvec;       // epilogue: q = mass2 * pvec - D in
+  double *partial;        // epilogue: Re<pvec, q> per rhs per 64-site wave, [n][ceil(V/2 / 64)]
+  const int *active;      // per-rhs mask or null
+};
+
+// SPB: sites per 256-thread workgroup (256: one tile per workgroup; 64: 4 tiles, one per wave).
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
+__global__ void __launch_bounds__(256) k_dslash(Args a) {
+  using C = typename CT<Real>::T;
+  constexpr int TPB = 256 / SPB;  // tiles per workgroup
+  const Geometry &g = a.g;
+  // XCD-aware order: the hardware deals workgroups round-robin to the 8 XCDs; each XCD gets a
+  // contiguous range of logical blocks (all rhs tiles of consecutive site blocks).
+  const int nb = a.nsblk * a.ngroups;
+  const int chunk = gridDim.x >> 3;
+  const int lb = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (lb >= nb) return;  // uniform for the whole workgroup
+  const int sblk = lb / a.ngroups;
+  const int grp = lb - sblk * a.ngroups;
+  const int tile = grp * TPB + (TPB == 1 ? 0 : int(threadIdx.x) / SPB);
+  const int r0 = tile * RT;
+  const unsigned vh = g.vh;
+  const unsigned s = sblk * SPB + (threadIdx.x % SPB);
+  const bool valid = s < vh && tile < a.ntiles;
+  const size_t tile_off = size_t(r0) * 3 * vh;
+  const C *__restrict__ in = static_cast<const C *>(a.in) + tile_off;
+  C *__restrict__ out = static_cast<C *>(a.out) + tile_off;
+  const LT *__restrict__ links = static_cast<const LT *>(a.links);
+
+  bool act[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) act[r] = valid && (r0 + r < a.n) && (!a.active || a.active[r0 + r]);
+
+  Real acc_re[RT][3], acc_im[RT][3];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc_re[r][c] = acc_im[r][c] = Real(0);
+
+  if (valid) {
+    const int xh = s % g.lxh;
+    int rest = s / g.lxh;
+    const int y = rest % g.ly;
+    rest /= g.ly;
+    const int z = rest % g.lz;
+    const int t = rest / g.lz;
+    const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+    const unsigned rowbase = s - xh;
+    constexpr int recon = R14 ? 14 : 18;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      unsigned f1, b1, f3, b3;
+      if (mu == 0) {
+        const int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
+        const int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
+        const int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
+        const int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
+        f1 = rowbase + (xf1 >> 1);
+        b1 = rowbase + (xb1 >> 1);
+        f3 = rowbase + (xf3 >> 1);
+        b3 = rowbase + (xb3 >> 1);
+      } else {
+        const int c = mu == 1 ? y : (mu == 2 ? z : t);
+        const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+        const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+        f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
+        b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
+        f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
+        b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
+      }
+      Lnk<Real> Lk;
+      load_link<Real, LT, false, NT>(links, link_plane(mu, recon), vh, s, Lk);
+      apply_hop<Real, RT, false>(Lk, in, vh, f1, act, acc_re, acc_im);
+      load_link<Real, LT, false, NT>(links, link_plane(4 + mu, recon), vh, s, Lk);
+      apply_hop<Real, RT, true>(Lk, in, vh, b1, act, acc_re, acc_im);
+      load_link<Real, LT, R14, NT>(links, link_plane(8 + mu, recon), vh, s, Lk);
+      apply_hop<Real, RT, false>(Lk, in, vh, f3, act, acc_re, acc_im);
+      load_link<Real, LT, R14, NT>(links, link_plane(12 + mu, recon), vh, s, Lk);
+      apply_hop<Real, RT, true>(Lk, in, vh, b3, act, acc_re, acc_im);
+    }
+  }
+
+  if constexpr (!EPI) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      if (!act[r]) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C o;
+        o.x = acc_re[r][c];
+        o.y = acc_im[r][c];
+        out[(unsigned)(r * 3 + c) * vh + s] = o;
+      }
+    }
+  } else {
+    // q = m^2 p - D_eo t, and per-rhs FP64 partials of Re<p, q> per 64-site wave (the same
+    // grouping for every workgroup shape, so the reduction is independent of the launch shape)
+    const C *__restrict__ pv = static_cast<const C *>(a.pvec) + tile_off;
+    const Real m2 = Real(a.mass2);
+    double dot[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      dot[r] = 0.0;
+      if (!act[r]) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C p = pv[(unsigned)(r * 3 + c) * vh + s];
+        C o;
+        o.x = fmaR(m2, p.x, -acc_re[r][c]);
+        o.y = fmaR(m2, p.y, -acc_im[r][c]);
+        out[(unsigned)(r * 3 + c) * vh + s] = o;
+        dot[r] = fma(double(p.x), double(o.x), dot[r]);
+        dot[r] = fma(double(p.y), double(o.y), dot[r]);
+      }
+    }
+    if (a.partial && tile < a.ntiles) {
+      const int lane = threadIdx.x & 63;
+      const unsigned wave_sites = s - lane;  // first site of this wave (SPB is a multiple of 64)
+      const unsigned nw = (vh + 63) / 64;
+      if (wave_sites < vh) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          double v = dot[r];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+          if (lane == 0 && r0 + r < a.n) a.partial[size_t(r0 + r) * nw + wave_sites / 64] = v;
+        }
+      }
+    }
+  }
+}
+
+using DslashFn = void (*)(const Args &, dim3, hipStream_t);
+
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
+void launch_t(const Args &a, dim3 grid, hipStream_t st) {
+  k_dslash<Real, LT, RT, R14, EPI, SPB, NT><<<grid, 256, 0, st>>>(a);
+}
+
+template <typename Real, typename LT, bool R14, bool EPI, int SPB, bool NT>
+DslashFn pick_rt(int rt) {
+  switch (rt) {
+    case 1: return launch_t<Real, LT, 1, R14, EPI, SPB, NT>;
+    case 2: return launch_t<Real, LT, 2, R14, EPI, SPB, NT>;
+    case 4: return launch_t<Real, LT, 4, R14, EPI, SPB, NT>;
+    case 8: return launch_t<Real, LT, 8, R14, EPI, SPB, NT>;
+    default:
+      if constexpr (!EPI && sizeof(Real) == 4) return launch_t<Real, LT, 16, R14, EPI, SPB, NT>;
+      return nullptr;
+  }
+}
+
+template <typename Real, typename LT, bool R14>
+DslashFn pick_all(bool epi, int rt, int spb, bool nt) {
+  if (epi) {
+    if (spb == 64) return nt ? pick_rt<Real, LT, R14, true, 64, true>(rt) : pick_rt<Real, LT, R14, true, 64, false>(rt);
+    return nt ? pick_rt<Real, LT, R14, true, 256, true>(rt) : pick_rt<Real, LT, R14, true, 256, false>(rt);
+  }
+  if (spb == 64) return nt ? pick_rt<Real, LT, R14, false, 64, true>(rt) : pick_rt<Real, LT, R14, false, 64, false>(rt);
+  return nt ? pick_rt<Real, LT, R14, false, 256, true>(rt) : pick_rt<Real, LT, R14, false, 256, false>(rt);
+}
+
+}  // namespace dslash
+
+// per-precision tables (dslash_f64.hip, dslash_f32.hip, dslash_f16.hip)
+dslash::DslashFn dslash_fn_f64(bool epi, int rt, int spb, bool nt);
+dslash::DslashFn dslash_fn_f32(bool epi, bool r14, int rt, int spb, bool nt);
+dslash::DslashFn dslash_fn_f16(bool epi, bool r14, int rt, int spb, bool nt);

@@ -50,7 +50,16 @@ enum WsSlot {
   WS_ERRPART,       // per-block reconstruction errors of hisq_load_links
   WS_CG0, WS_CG1, WS_CG2, WS_CG3, WS_CG4, WS_CG5, WS_CG6, WS_CG7,
   WS_NN0, WS_NN1, WS_NN2, WS_NN3, WS_NN4, WS_NN5, WS_NN6, WS_NN7,
+  WS_TUNE0, WS_TUNE1, WS_TUNE2,  // launch-configuration tuning scratch (freed after tuning)
   WS_COUNT
+};
+
+// Launch configuration of the Dslash for one (precision, n, plain/fused-M) key.
+struct TuneEntry {
+  enum State { NONE = 0, HEURISTIC, TUNED, FORCED };
+  hisq_launch cfg{};
+  State state = NONE;
+  float ms = 0.f;
 };
 
 struct NNState;
@@ -65,6 +74,7 @@ struct hisq_ctx {
   LinkCopy links[3];                 // indexed by HISQ_F64 / HISQ_F32 / HISQ_F16
   void *ws[WS_COUNT] = {};
   size_t ws_bytes[WS_COUNT] = {};
+  TuneEntry tune[3][HISQ_MAX_RHS + 1][2];
   void *pinned = nullptr;            // pinned host mirror of per-rhs residuals
   size_t pinned_bytes = 0;
   NNState *nn = nullptr;
@@ -104,11 +114,15 @@ int launch_pack_links(hisq_ctx *ctx, const double *fat, const double *naik, int 
                       int parity, void *dst, double *max_recon_err_host);
 
 // out = D_{out_parity,1-out_parity} in  (epi = false), or for out_parity = 0 with epi = true:
-// out = mass2 * pvec - D_eo in and, if partial != nullptr, per-block partials of Re<pvec, out>
-// written to partial[r * nblk + b], nblk returned in *nblk_out.
+// out = mass2 * pvec - D_eo in and, if partial != nullptr, per-64-site partials of
+// Re<pvec, out> written to partial[r * nblk + b], nblk (= dslash_partials) in *nblk_out.
+// active: per-rhs mask (rhs with active[r] == 0 are neither read nor written), or null.
 int launch_dslash(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *out,
                   bool epi, double mass2, const void *pvec, double *partial, int *nblk_out,
                   const int *active = nullptr);
+
+// Number of per-rhs partials the fused-M Dslash writes (one per 64-site wave).
+int dslash_partials(const Geometry &g);
 
 // Sum partial[r * nblk + b] over b for r < n in a fixed order into res[r] (device).
 int launch_reduce_partials(hisq_ctx *ctx, const double *partial, int n, int nblk, int width,

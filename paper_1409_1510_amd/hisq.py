@@ -46,6 +46,14 @@ class HisqError(RuntimeError):
         self.code = code
 
 
+class hisq_launch(ctypes.Structure):
+    _fields_ = [("rhs_per_thread", ctypes.c_int), ("sites_per_block", ctypes.c_int),
+                ("nontemporal_links", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.rhs_per_thread, self.sites_per_block, self.nontemporal_links)
+
+
 class hisq_cg_params(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("reliable_every", ctypes.c_int), ("link_prec", ctypes.c_int),
@@ -84,6 +92,9 @@ def _load():
         "hisq_dslash_mrhs": (cint, [vp, cint, cint, cint, vp, vp]),
         "hisq_apply_m": (cint, [vp, cint, cd, cint, vp, vp, vp]),
         "hisq_dot_mrhs": (cint, [vp, cint, cint, vp, vp, vp]),
+        "hisq_set_launch": (cint, [vp, cint, cint, ctypes.POINTER(hisq_launch)]),
+        "hisq_get_launch": (cint, [vp, cint, cint, cint, ctypes.POINTER(hisq_launch)]),
+        "hisq_autotune": (cint, [vp, cint, cint, cint, ctypes.POINTER(hisq_launch), dp]),
         "hisq_cg_mrhs": (cint, [vp, cd, cint, vp, vp, ctypes.POINTER(hisq_cg_params),
                                 ctypes.POINTER(hisq_cg_stats)]),
     }
@@ -186,6 +197,26 @@ def hisq_apply_m(ctx, prec: int, mass: float, n: int, inp, out, pq_out=None) -> 
 
 def hisq_dot_mrhs(ctx, prec: int, n: int, a, b, dots) -> None:
     _check(ctx, _lib.hisq_dot_mrhs(ctx, int(prec), int(n), _ptr(a), _ptr(b), _ptr(dots)))
+
+
+def hisq_set_launch(ctx, prec: int, n: int, cfg=None) -> None:
+    """cfg: (rhs_per_thread, sites_per_block, nontemporal_links), a hisq_launch, or None."""
+    if cfg is not None and not isinstance(cfg, hisq_launch):
+        cfg = hisq_launch(*cfg)
+    _check(ctx, _lib.hisq_set_launch(ctx, int(prec), int(n), ctypes.byref(cfg) if cfg is not None else None))
+
+
+def hisq_get_launch(ctx, prec: int, n: int, fused_m: int = 0) -> tuple:
+    c = hisq_launch()
+    _check(ctx, _lib.hisq_get_launch(ctx, int(prec), int(n), int(fused_m), ctypes.byref(c)))
+    return c.as_tuple()
+
+
+def hisq_autotune(ctx, prec: int, n: int, fused_m: int = 0):
+    c = hisq_launch()
+    ms = ctypes.c_double()
+    _check(ctx, _lib.hisq_autotune(ctx, int(prec), int(n), int(fused_m), ctypes.byref(c), ctypes.byref(ms)))
+    return c.as_tuple(), ms.value
 
 
 def hisq_cg_mrhs(ctx, mass: float, n: int, b, x, params: hisq_cg_params, stats: hisq_cg_stats):

@@ -197,3 +197,50 @@ def test_full_size_32c8_sampled_sites():
     rhs = lat.dot(hisq.HISQ_F64, a, lat.dslash(0, hisq.HISQ_F64, b))   # <a, D_eo b>  (even)
     assert torch.max(torch.abs(lhs + rhs)) <= 1e-10 * torch.max(torch.abs(lhs))
     lat.close()
+
+
+ALL_CFGS = [(rt, spb, nt) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
+
+
+@pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
+                                        (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14)])
+def test_every_launch_config_bit_identical(prec, recon):
+    """All register tiles, workgroup shapes and cache hints give the same bits, for the plain
+    half Dslash and for the fused M operator (including its FP64 <p, Mp> reduction), and the
+    autotuned choice is one of them."""
+    dims, n, mass = (8, 6, 4, 10), 11, 0.1
+    lat, fat, naik = make_lattice(dims, 120, recon=recon)
+    dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
+    rdt = torch.float64 if prec == hisq.HISQ_F64 else torch.float32
+    v = torch.from_numpy(_vecs(dims, n, 121)).to(DEV).to(dt)
+    ref = oracle.dslash_half(fat, naik, _vecs(dims, n, 121), dims, 1)
+    first = None
+    tried = 0
+    for cfg in ALL_CFGS:
+        try:
+            hisq.hisq_set_launch(lat.ctx, prec, n, cfg)
+        except hisq.HisqError as e:
+            assert e.code == hisq.HISQ_ERR_ARG and prec == hisq.HISQ_F64 and cfg[0] == 16
+            continue
+        tried += 1
+        out = lat.dslash(1, prec, v)
+        m, pq = lat.apply_m(prec, mass, v, with_pq=True)
+        cur = (out.view(rdt).clone(), m.view(rdt).clone(), pq.clone())
+        if first is None:
+            first = cur
+            got = out.cpu().numpy()
+            if prec == hisq.HISQ_F64:
+                assert rel_elem(got, ref) <= 1e-13
+            else:
+                assert rel_l2(got, ref) <= (2e-3 if prec == hisq.HISQ_F16 else 1e-6)
+        else:
+            assert torch.equal(first[0], cur[0]), cfg
+            assert torch.equal(first[1], cur[1]), cfg
+            assert torch.equal(first[2], cur[2]), cfg
+    assert tried >= 16
+    hisq.hisq_set_launch(lat.ctx, prec, n, None)
+    best, ms = hisq.hisq_autotune(lat.ctx, prec, n, 0)
+    assert best in ALL_CFGS and ms > 0
+    assert hisq.hisq_get_launch(lat.ctx, prec, n, 0) == best
+    assert torch.equal(lat.dslash(1, prec, v).view(rdt), first[0])
+    lat.close()

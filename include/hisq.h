@@ -126,6 +126,10 @@ typedef struct {
   int sites_per_block;   /* 256: one rhs tile per 256-thread workgroup; 64: the 4 waves of a     */
                          /*      workgroup take 4 rhs tiles of the same 64 sites               */
   int nontemporal_links; /* 1: link loads carry the non-temporal cache hint                     */
+  int lds_links;         /* 1 (2): a workgroup of 64 sites x 4 (8) waves stages its sites' links */
+                         /*    in LDS and its waves loop over the rhs tiles (requires            */
+                         /*    sites_per_block = 64, rhs_per_thread <= 4, nontemporal_links = 0, */
+                         /*    and LDS for 64 sites' links: not FP64)                            */
 } hisq_launch;
 
 /* Force the configuration for (prec, n), both forms (the fused-M form clamps rhs_per_thread to

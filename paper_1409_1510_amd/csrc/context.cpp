@@ -115,6 +115,10 @@ int hisq_create(hisq_ctx **out, const int dims[4], int device, void *stream) {
   g.st = g.lxh * g.ly * g.lz;
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(stream);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+      lds > 0)
+    ctx->lds_max = size_t(lds);
   *out = ctx;
   return HISQ_OK;
 }

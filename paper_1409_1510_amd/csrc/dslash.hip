@@ -11,18 +11,28 @@ using dslash::DslashFn;
 namespace {
 
 DslashFn lookup(int prec, int recon, bool epi, const hisq_launch &c) {
-  if (prec == HISQ_F64) return dslash_fn_f64(epi, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links);
+  const int lds = c.lds_links;
+  if (prec == HISQ_F64)
+    return dslash_fn_f64(epi, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
   if (prec == HISQ_F32)
-    return dslash_fn_f32(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links);
-  return dslash_fn_f16(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links);
+    return dslash_fn_f32(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
+  return dslash_fn_f16(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
 }
 
-bool config_valid(int prec, bool epi, const hisq_launch &c) {
+size_t lds_bytes(int prec, int recon, const hisq_launch &c) {
+  if (!c.lds_links) return 0;
+  const size_t elem = prec == HISQ_F64 ? 16 : (prec == HISQ_F32 ? 8 : 4);
+  return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem;
+}
+
+bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size_t lds_max = 0) {
+  if (c.lds_links && lds_max && lds_bytes(prec, recon, c) > lds_max) return false;
   const int rt = c.rhs_per_thread;
   if (rt != 1 && rt != 2 && rt != 4 && rt != 8 && rt != 16) return false;
   if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
-  return lookup(prec, 18, epi, c) != nullptr;
+  if (c.lds_links < 0 || c.lds_links > 2) return false;
+  return lookup(prec, 18, epi, c) != nullptr && lookup(prec, 14, epi, c) != nullptr;
 }
 
 int next_pow2(int n) {
@@ -36,7 +46,7 @@ hisq_launch heuristic(int prec, int n, bool epi) {
   int cap = (prec == HISQ_F64 || epi) ? 4 : 8;
   int rt = 1;
   while (rt * 2 <= cap && rt * 2 <= n) rt *= 2;
-  return hisq_launch{rt, 256, 0};
+  return hisq_launch{rt, 256, 0, 0};
 }
 
 struct Geo {
@@ -47,7 +57,7 @@ Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
   Geo o;
   o.ntiles = (n + c.rhs_per_thread - 1) / c.rhs_per_thread;
   const int tpb = 256 / c.sites_per_block;
-  o.ngroups = (o.ntiles + tpb - 1) / tpb;
+  o.ngroups = c.lds_links ? 1 : (o.ntiles + tpb - 1) / tpb;  // the LDS form loops over the tiles
   o.nsblk = (g.vh + c.sites_per_block - 1) / c.sites_per_block;
   const int nb = o.nsblk * o.ngroups;
   o.grid = (nb + 7) / 8 * 8;
@@ -59,6 +69,9 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
   const LinkCopy &l = ctx->links[prec];
   DslashFn fn = lookup(prec, l.recon, epi, c);
   if (!fn) return set_err(ctx, HISQ_ERR_ARG, "invalid Dslash launch configuration");
+  if (lds_bytes(prec, l.recon, c) > ctx->lds_max)
+    return set_err(ctx, HISQ_ERR_ARG, "Dslash launch configuration needs %zu bytes of LDS (%zu available)",
+                   lds_bytes(prec, l.recon, c), ctx->lds_max);
   const Geo geo = geometry(ctx->g, n, c);
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
          mass2, pvec, partial, active};
@@ -97,9 +110,10 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   for (int rt : rts) {
     if (rt > next_pow2(n)) break;
     for (int spb : {256, 64})
-      for (int nt : {0, 1}) {
-        hisq_launch c{rt, spb, nt};
-        if (!config_valid(prec, epi, c)) continue;
+      for (int nt : {0, 1})
+        for (int lds : {0, 1, 2}) {
+        hisq_launch c{rt, spb, nt, lds};
+        if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
         const int reps = 3;
         for (int k = 0; k <= reps && rc == HISQ_OK; ++k) {
           if (k == 1) (void)hipEventRecord(e0, ctx->stream);
@@ -173,11 +187,13 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
       continue;
     }
     hisq_launch c = *cfg;
-    if (!config_valid(prec, epi, c)) {
+    const int recon = ctx->links[prec].base ? ctx->links[prec].recon : 18;
+    if (!config_valid(prec, epi, c, recon, ctx->lds_max)) {
       if (epi) {  // the fused-M form caps the register tile: use the largest valid one
-        while (c.rhs_per_thread > 1 && !config_valid(prec, true, c)) c.rhs_per_thread /= 2;
+        while (c.rhs_per_thread > 1 && !config_valid(prec, true, c, recon, ctx->lds_max))
+          c.rhs_per_thread /= 2;
       }
-      if (!config_valid(prec, epi, c))
+      if (!config_valid(prec, epi, c, recon, ctx->lds_max))
         return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: invalid configuration (rt %d, spb %d, nt %d)",
                        cfg->rhs_per_thread, cfg->sites_per_block, cfg->nontemporal_links);
     }

@@ -266,11 +266,169 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
   }
 }
 
+// LDS-staged form: a workgroup of 64 sites x WPB waves first copies the links of its 64 sites
+// (all 16 hops) into LDS, then the waves loop over the rhs tiles (wave w takes tiles w, w+WPB,
+// ...), reading the links from LDS for every tile.  Only WPB*RT rhs of a site block are in
+// flight at a time, so the neighbour vectors other workgroups gather are far more likely to be
+// found in L2 than when every thread holds all n rhs; the links still come from HBM once.
+// Same site order, hop order and FMA sequence per rhs as k_dslash (bit-identical output), and
+// the same per-64-site grouping of the fused <p, Mp> partials.
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB>
+__global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
+  static_assert(WPB == 4 || WPB == 8, "4 or 8 waves per workgroup");
+  using C = typename CT<Real>::T;
+  constexpr int recon = R14 ? 14 : 18;
+  constexpr int PL = R14 ? 128 : 144;  // stored planes per site
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LT *sl = reinterpret_cast<LT *>(smem_raw);
+  const Geometry &g = a.g;
+  const int chunk = gridDim.x >> 3;
+  const int sblk = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+  if (sblk >= a.nsblk) return;  // uniform for the whole workgroup
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned vh = g.vh;
+  const unsigned s = sblk * 64 + lane;
+  const bool valid = s < vh;
+  const LT *__restrict__ links = static_cast<const LT *>(a.links);
+  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access)
+  for (int pl = wave; pl < PL; pl += WPB)
+    if (valid) sl[pl * 64 + lane] = links[size_t(pl) * vh + s];
+  __syncthreads();
+
+  int x = 0, y = 0, z = 0, t = 0;
+  if (valid) {
+    const int xh = s % g.lxh;
+    int rest = s / g.lxh;
+    y = rest % g.ly;
+    rest /= g.ly;
+    z = rest % g.lz;
+    t = rest / g.lz;
+    x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+  }
+  const unsigned rowbase = s - (x >> 1);
+
+  for (int tile = wave; tile < a.ntiles; tile += WPB) {
+    const int r0 = tile * RT;
+    const size_t tile_off = size_t(r0) * 3 * vh;
+    const C *__restrict__ in = static_cast<const C *>(a.in) + tile_off;
+    C *__restrict__ out = static_cast<C *>(a.out) + tile_off;
+    bool act[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) act[r] = valid && (r0 + r < a.n) && (!a.active || a.active[r0 + r]);
+    Real acc_re[RT][3], acc_im[RT][3];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc_re[r][c] = acc_im[r][c] = Real(0);
+    // hop order as in k_dslash: per mu, fat fwd, fat bwd, Naik fwd, Naik bwd
+    if (valid) {
+#pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        unsigned f1, b1, f3, b3;
+        if (mu == 0) {
+          const int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
+          const int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
+          const int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
+          const int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
+          f1 = rowbase + (xf1 >> 1);
+          b1 = rowbase + (xb1 >> 1);
+          f3 = rowbase + (xf3 >> 1);
+          b3 = rowbase + (xb3 >> 1);
+        } else {
+          const int c = mu == 1 ? y : (mu == 2 ? z : t);
+          const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+          const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+          f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
+          b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
+          f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
+          b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
+        }
+        Lnk<Real> Lk;
+        load_link<Real, LT, false, false>(sl, link_plane(mu, recon), 64u, lane, Lk);
+        apply_hop<Real, RT, false>(Lk, in, vh, f1, act, acc_re, acc_im);
+        load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
+        apply_hop<Real, RT, true>(Lk, in, vh, b1, act, acc_re, acc_im);
+        load_link<Real, LT, R14, false>(sl, link_plane(8 + mu, recon), 64u, lane, Lk);
+        apply_hop<Real, RT, false>(Lk, in, vh, f3, act, acc_re, acc_im);
+        load_link<Real, LT, R14, false>(sl, link_plane(12 + mu, recon), 64u, lane, Lk);
+        apply_hop<Real, RT, true>(Lk, in, vh, b3, act, acc_re, acc_im);
+      }
+    }
+    if constexpr (!EPI) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        if (!act[r]) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          C o;
+          o.x = acc_re[r][c];
+          o.y = acc_im[r][c];
+          out[(unsigned)(r * 3 + c) * vh + s] = o;
+        }
+      }
+    } else {
+      const C *__restrict__ pv = static_cast<const C *>(a.pvec) + tile_off;
+      const Real m2 = Real(a.mass2);
+      double dot[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        dot[r] = 0.0;
+        if (!act[r]) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C p = pv[(unsigned)(r * 3 + c) * vh + s];
+          C o;
+          o.x = fmaR(m2, p.x, -acc_re[r][c]);
+          o.y = fmaR(m2, p.y, -acc_im[r][c]);
+          out[(unsigned)(r * 3 + c) * vh + s] = o;
+          dot[r] = fma(double(p.x), double(o.x), dot[r]);
+          dot[r] = fma(double(p.y), double(o.y), dot[r]);
+        }
+      }
+      if (a.partial) {
+        const unsigned nw = (vh + 63) / 64;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          double v = dot[r];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+          if (lane == 0 && r0 + r < a.n) a.partial[size_t(r0 + r) * nw + sblk] = v;
+        }
+      }
+    }
+  }
+}
+
 using DslashFn = void (*)(const Args &, dim3, hipStream_t);
 
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
 void launch_t(const Args &a, dim3 grid, hipStream_t st) {
   k_dslash<Real, LT, RT, R14, EPI, SPB, NT><<<grid, 256, 0, st>>>(a);
+}
+
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB>
+void launch_lds(const Args &a, dim3 grid, hipStream_t st) {
+  constexpr size_t lds = size_t(R14 ? 128 : 144) * 64 * sizeof(LT);
+  k_dslash_lds<Real, LT, RT, R14, EPI, WPB><<<grid, 64 * WPB, lds, st>>>(a);
+}
+
+// lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves
+template <typename Real, typename LT, bool R14, bool EPI>
+DslashFn pick_lds(int rt, int lds) {
+  if constexpr (sizeof(LT) > 8) return nullptr;  // FP64 links do not fit LDS twice per CU
+  if (lds == 1) switch (rt) {
+      case 1: return launch_lds<Real, LT, 1, R14, EPI, 4>;
+      case 2: return launch_lds<Real, LT, 2, R14, EPI, 4>;
+      case 4: return launch_lds<Real, LT, 4, R14, EPI, 4>;
+      default: return nullptr;
+    }
+  if (lds == 2) switch (rt) {
+      case 1: return launch_lds<Real, LT, 1, R14, EPI, 8>;
+      case 2: return launch_lds<Real, LT, 2, R14, EPI, 8>;
+      case 4: return launch_lds<Real, LT, 4, R14, EPI, 8>;
+      default: return nullptr;
+    }
+  return nullptr;
 }
 
 template <typename Real, typename LT, bool R14, bool EPI, int SPB, bool NT>
@@ -287,7 +445,11 @@ DslashFn pick_rt(int rt) {
 }
 
 template <typename Real, typename LT, bool R14>
-DslashFn pick_all(bool epi, int rt, int spb, bool nt) {
+DslashFn pick_all(bool epi, int rt, int spb, bool nt, int lds) {
+  if (lds) {
+    if (spb != 64 || nt) return nullptr;
+    return epi ? pick_lds<Real, LT, R14, true>(rt, lds) : pick_lds<Real, LT, R14, false>(rt, lds);
+  }
   if (epi) {
     if (spb == 64) return nt ? pick_rt<Real, LT, R14, true, 64, true>(rt) : pick_rt<Real, LT, R14, true, 64, false>(rt);
     return nt ? pick_rt<Real, LT, R14, true, 256, true>(rt) : pick_rt<Real, LT, R14, true, 256, false>(rt);
@@ -299,6 +461,6 @@ DslashFn pick_all(bool epi, int rt, int spb, bool nt) {
 }  // namespace dslash
 
 // per-precision tables (dslash_f64.hip, dslash_f32.hip, dslash_f16.hip)
-dslash::DslashFn dslash_fn_f64(bool epi, int rt, int spb, bool nt);
-dslash::DslashFn dslash_fn_f32(bool epi, bool r14, int rt, int spb, bool nt);
-dslash::DslashFn dslash_fn_f16(bool epi, bool r14, int rt, int spb, bool nt);
+dslash::DslashFn dslash_fn_f64(bool epi, int rt, int spb, bool nt, int lds);
+dslash::DslashFn dslash_fn_f32(bool epi, bool r14, int rt, int spb, bool nt, int lds);
+dslash::DslashFn dslash_fn_f16(bool epi, bool r14, int rt, int spb, bool nt, int lds);

@@ -67,6 +67,7 @@ struct NNState;
 struct hisq_ctx {
   Geometry g{};
   int device = 0;
+  size_t lds_max = 65536;            // dynamic LDS bytes a workgroup may use on this device
   hipStream_t stream = nullptr;
   std::string err;
   bool links_loaded = false;

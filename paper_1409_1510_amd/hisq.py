@@ -48,10 +48,10 @@ class HisqError(RuntimeError):
 
 class hisq_launch(ctypes.Structure):
     _fields_ = [("rhs_per_thread", ctypes.c_int), ("sites_per_block", ctypes.c_int),
-                ("nontemporal_links", ctypes.c_int)]
+                ("nontemporal_links", ctypes.c_int), ("lds_links", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.rhs_per_thread, self.sites_per_block, self.nontemporal_links)
+        return (self.rhs_per_thread, self.sites_per_block, self.nontemporal_links, self.lds_links)
 
 
 class hisq_cg_params(ctypes.Structure):
@@ -200,7 +200,8 @@ def hisq_dot_mrhs(ctx, prec: int, n: int, a, b, dots) -> None:
 
 
 def hisq_set_launch(ctx, prec: int, n: int, cfg=None) -> None:
-    """cfg: (rhs_per_thread, sites_per_block, nontemporal_links), a hisq_launch, or None."""
+    """cfg: (rhs_per_thread, sites_per_block, nontemporal_links, lds_links), a hisq_launch, or
+    None."""
     if cfg is not None and not isinstance(cfg, hisq_launch):
         cfg = hisq_launch(*cfg)
     _check(ctx, _lib.hisq_set_launch(ctx, int(prec), int(n), ctypes.byref(cfg) if cfg is not None else None))

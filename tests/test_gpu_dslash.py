@@ -199,15 +199,16 @@ def test_full_size_32c8_sampled_sites():
     lat.close()
 
 
-ALL_CFGS = [(rt, spb, nt) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
+ALL_CFGS = ([(rt, spb, nt, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
+            + [(rt, 64, 0, lds) for rt in (1, 2, 4) for lds in (1, 2)])
 
 
 @pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
                                         (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14)])
 def test_every_launch_config_bit_identical(prec, recon):
-    """All register tiles, workgroup shapes and cache hints give the same bits, for the plain
-    half Dslash and for the fused M operator (including its FP64 <p, Mp> reduction), and the
-    autotuned choice is one of them."""
+    """All register tiles, workgroup shapes, cache hints and the LDS-staged form give the same
+    bits, for the plain half Dslash and for the fused M operator (including its FP64 <p, Mp>
+    reduction), and the autotuned choice is one of them."""
     dims, n, mass = (8, 6, 4, 10), 11, 0.1
     lat, fat, naik = make_lattice(dims, 120, recon=recon)
     dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
@@ -219,8 +220,9 @@ def test_every_launch_config_bit_identical(prec, recon):
     for cfg in ALL_CFGS:
         try:
             hisq.hisq_set_launch(lat.ctx, prec, n, cfg)
-        except hisq.HisqError as e:
-            assert e.code == hisq.HISQ_ERR_ARG and prec == hisq.HISQ_F64 and cfg[0] == 16
+        except hisq.HisqError as e:  # FP64 rt 16, FP64 LDS form, or LDS beyond the device limit
+            assert e.code == hisq.HISQ_ERR_ARG
+            assert (prec == hisq.HISQ_F64 and (cfg[0] == 16 or cfg[3])) or cfg[3]
             continue
         tried += 1
         out = lat.dslash(1, prec, v)
@@ -238,6 +240,7 @@ def test_every_launch_config_bit_identical(prec, recon):
             assert torch.equal(first[1], cur[1]), cfg
             assert torch.equal(first[2], cur[2]), cfg
     assert tried >= 16
+    print(f"prec {prec} r{recon}: {tried} launch configurations agree bit for bit")
     hisq.hisq_set_launch(lat.ctx, prec, n, None)
     best, ms = hisq.hisq_autotune(lat.ctx, prec, n, 0)
     assert best in ALL_CFGS and ms > 0

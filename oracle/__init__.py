@@ -17,3 +17,4 @@ from .dslash import (  # noqa: F401
     dslash_full, dslash_half, dslash_sites, embed, extract, m_ee, parity_lex, site_coords,
 )
 from .cg import cg, true_residual  # noqa: F401
+from . import nn  # noqa: F401

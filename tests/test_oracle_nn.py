@@ -1,0 +1,126 @@
+"""Pins of the network oracle (forward, loss, Wirtinger gradients).
+
+Independent facts used: central finite differences of the loss (gradients), a two-layer
+one-channel closed form written with explicit site indexing (hop directions and daggers), the
+fat-link part of Eq. 3 (the stencil with weights +1 forward / -1 backward is the fat Dslash),
+gauge covariance and linearity.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import nn
+
+DIMS = (4, 4, 4, 6)
+
+
+def _rand_theta(c, l, seed, scale=0.5):
+    g = np.random.Generator(np.random.Philox(key=seed))
+    k = nn.n_params(c, l)
+    return (g.standard_normal(k) + 1j * g.standard_normal(k)) * scale
+
+
+def test_param_count_and_pack_roundtrip():
+    assert nn.n_params(8, 4) == 496
+    th = _rand_theta(3, 3, 1)
+    assert np.array_equal(nn.pack(nn.unpack(th, 3, 3)), th)
+
+
+@pytest.mark.parametrize("c,l", [(2, 2), (3, 3)])
+def test_gradient_matches_finite_differences(c, l):
+    fat, _ = synth.gauge_links(DIMS, 31)
+    th = _rand_theta(c, l, 32)
+    rs = synth.sources(DIMS, 2, 33)
+    ys = synth.sources(DIMS, 2, 34)
+    val, grad = nn.loss_and_grad(th, fat, rs, ys, DIMS, c, l)
+    assert abs(val - nn.loss(th, fat, rs, ys, DIMS, c, l)) < 1e-12 * val
+    rng = np.random.default_rng(3)
+    idx = rng.choice(th.size, 12, replace=False)
+    h = 1e-6
+    for k in idx:
+        e = np.zeros_like(th)
+        e[k] = h
+        d_re = (nn.loss(th + e, fat, rs, ys, DIMS, c, l) - nn.loss(th - e, fat, rs, ys, DIMS, c, l)) / (2 * h)
+        d_im = (nn.loss(th + 1j * e, fat, rs, ys, DIMS, c, l) - nn.loss(th - 1j * e, fat, rs, ys, DIMS, c, l)) / (2 * h)
+        scale = max(abs(grad[k]), 1e-3 * np.max(np.abs(grad)))
+        assert abs(grad[k].real - d_re) <= 1e-6 * scale, (k, grad[k], d_re)
+        assert abs(grad[k].imag - d_im) <= 1e-6 * scale, (k, grad[k], d_im)
+
+
+def _coords(dims):
+    lx, ly, lz, lt = dims
+    lex = np.arange(lx * ly * lz * lt)
+    return np.stack([lex % lx, (lex // lx) % ly, (lex // (lx * ly)) % lz, lex // (lx * ly * lz)], 1)
+
+
+def _shift(dims, mu, k):
+    c = _coords(dims)
+    c[:, mu] = (c[:, mu] + k) % dims[mu]
+    lx, ly, lz, lt = dims
+    return c[:, 0] + lx * (c[:, 1] + ly * (c[:, 2] + lz * c[:, 3]))
+
+
+@pytest.mark.parametrize("mu", [0, 2, 3])
+def test_two_layer_closed_form(mu):
+    """C = 1, layer 1 = forward hop only, layer 2 = backward hop only:
+    z(x) = X(x-mu,mu)^dag X(x-mu,mu) r(x) on every even site x."""
+    fat, _ = synth.gauge_links(DIMS, 35)
+    p = nn.unpack(np.zeros(nn.n_params(1, 2), complex), 1, 2)
+    p["W_in"][0] = 1.0
+    p["W_out"][0] = 1.0
+    p["W"][0][0, 0] = 1.0
+    p["a"][0][1 + mu, 0] = 1.0
+    p["a"][1][5 + mu, 0] = 1.0
+    r = synth.sources(DIMS, 1, 36)[0]
+    z = nn.forward(nn.pack(p), fat, r, DIMS, 1, 2)
+    ev = oracle.parity_lex(DIMS, 0)
+    back = _shift(DIMS, mu, -1)[ev]
+    u = fat[back, mu]                                   # X(x - mu, mu) for even x
+    expect = np.einsum("sba,sbc,cs->as", np.conj(u), u, r)  # (U^dag U r)_a
+    assert np.max(np.abs(z - expect)) < 1e-13
+
+
+def test_stencil_with_dslash_weights_is_fat_dslash():
+    """Weights 0 (self), +1 (forward), -1 (backward) give the fat-link part of Eq. 3, so two
+    layers give D_eo D_oe with the Naik links set to zero."""
+    fat, _ = synth.gauge_links(DIMS, 37)
+    p = nn.unpack(np.zeros(nn.n_params(1, 2), complex), 1, 2)
+    p["W_in"][0] = p["W_out"][0] = p["W"][0][0, 0] = 1.0
+    for l in range(2):
+        p["a"][l][1:5, 0] = 1.0
+        p["a"][l][5:9, 0] = -1.0
+    r = synth.sources(DIMS, 1, 38)
+    z = nn.forward(nn.pack(p), fat, r[0], DIMS, 1, 2)
+    zero = np.zeros_like(fat)
+    ref = oracle.dslash_half(fat, zero, oracle.dslash_half(fat, zero, r, DIMS, 1), DIMS, 0)[0]
+    assert np.max(np.abs(z - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_gauge_covariance_and_linearity():
+    c, l = 3, 4
+    fat, _ = synth.gauge_links(DIMS, 39)
+    th = _rand_theta(c, l, 40)
+    vol = int(np.prod(DIMS))
+    om = synth.haar_su3(np.random.Generator(np.random.Philox(key=41)), vol)
+    omd = np.conj(np.swapaxes(om, -1, -2))
+    fat_g = np.empty_like(fat)
+    for mu in range(4):
+        fat_g[:, mu] = om @ fat[:, mu] @ omd[_shift(DIMS, mu, 1)]
+    ev = oracle.parity_lex(DIMS, 0)
+    r = synth.sources(DIMS, 2, 42)
+    rg = np.einsum("sab,bs->as", om[ev], r[0])
+    z = nn.forward(th, fat, r[0], DIMS, c, l)
+    zg = nn.forward(th, fat_g, rg, DIMS, c, l)
+    assert np.max(np.abs(zg - np.einsum("sab,bs->as", om[ev], z))) < 1e-11 * np.max(np.abs(z))
+    al, be = 0.3 - 0.7j, 1.1 + 0.2j
+    z2 = nn.forward(th, fat, r[1], DIMS, c, l)
+    zc = nn.forward(th, fat, al * r[0] + be * r[1], DIMS, c, l)
+    assert np.max(np.abs(zc - al * z - be * z2)) < 1e-11 * np.max(np.abs(zc))
+
+
+def test_init_is_near_identity():
+    th = nn.init_params(8, 4, 5, scale=0.0)
+    fat, _ = synth.gauge_links(DIMS, 43)
+    r = synth.sources(DIMS, 1, 44)[0]
+    assert np.max(np.abs(nn.forward(th, fat, r, DIMS, 8, 4) - r)) < 1e-14

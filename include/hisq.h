@@ -178,6 +178,46 @@ typedef struct {
 int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
                  const hisq_cg_params *p, hisq_cg_stats *stats);
 
+/* ---- learned gauge-covariant preconditioner ------------------------------------------------
+ * A linear network z = P r on the even sites, for the flexible CG (HISQ_FCG_NN).  Layer l mixes
+ * the C = 8 complex channels per site and colour (C x C complex matrix W_l; the first layer lifts
+ * the one input channel with W_in[C], the output is read out with W_out[C]) and applies a
+ * per-channel gauge-covariant one-hop stencil over the fat links X of Eq. 3:
+ *   S(a, phi)_c(x) = a[0,c] phi_c(x) + sum_mu (a[1+mu,c] X(x,mu) phi_c(x+mu)
+ *                                            + a[5+mu,c] X(x-mu,mu)^dag phi_c(x-mu)).
+ * Parameters (complex; as reals, re/im interleaved), in this order: W_in[C]; for l = 1..L:
+ * W_l[C][C] ([out][in], only for l >= 2) then a_l[9][C]; W_out[C].  Hop index: 0 self, 1+mu
+ * forward, 5+mu backward.  Activations are stored in BF16 (default; channel mixing on bf16 MFMA)
+ * or FP32, arithmetic FP32, master weights FP32.  Needs the FP32 or FP16 link copy. */
+
+/* Create the network (replaces an existing one): layers 1..8, channels must be 8; weights start
+ * near P = identity with a small pseudo-random perturbation drawn from seed. */
+int hisq_nn_init(hisq_ctx *ctx, int layers, int channels, unsigned long long seed);
+/* Number of complex parameters (>= 1), or a negative error code. */
+int hisq_nn_num_params(hisq_ctx *ctx);
+/* Copy the parameters out of / into the context (host arrays of 2 * hisq_nn_num_params reals).
+ * Setting resets the optimiser state. */
+int hisq_nn_get_params(hisq_ctx *ctx, double *out, int n_reals);
+int hisq_nn_set_params(hisq_ctx *ctx, const double *in, int n_reals);
+/* Activation storage: 1 = BF16 (default), 0 = FP32. */
+int hisq_nn_set_precision(hisq_ctx *ctx, int bf16_storage);
+/* z = P r for n vectors: r, z device [n][3][V/2] on even sites, complex128 (prec_io = HISQ_F64)
+ * or complex64 (HISQ_F32).  Asynchronous. */
+int hisq_nn_apply(hisq_ctx *ctx, int n, int prec_io, const void *r, void *z);
+/* Loss L = (1/n) sum_j ||P r_j - y_j||^2 / ||y_j||^2 and its gradient with respect to the
+ * parameters (Wirtinger: dL/dRe + i dL/dIm, 2 * num_params reals, host) for n pairs r, y (device
+ * complex128 [n][3][V/2]).  loss and grad may be NULL.  Synchronises. */
+int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void *y, double *loss, double *grad);
+/* Train on n_pairs pairs (device complex128 [n_pairs][3][V/2] each) with Adam (lr, beta1 0.9,
+ * beta2 0.999), minibatches of `batch` consecutive pairs visited in a seeded random order, for
+ * `epochs` passes.  loss_history (host, epochs doubles, may be NULL) receives the mean minibatch
+ * loss of each epoch.  Synchronises. */
+int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const void *y, int epochs, int batch,
+                  double lr, unsigned long long seed, double *loss_history);
+/* Save / load the parameters (binary: 4 int32 header, then the reals as float64). */
+int hisq_nn_save(hisq_ctx *ctx, const char *path);
+int hisq_nn_load(hisq_ctx *ctx, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

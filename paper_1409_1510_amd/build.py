@@ -38,12 +38,31 @@ def _compile(src: str) -> str:
     return obj
 
 
+def hip_runtime_dir() -> str:
+    """Directory of the HIP runtime PyTorch loads (torch/lib ships its own libamdhip64.so).
+
+    libhisq links that same runtime: two HIP runtimes in one process do not share the device,
+    and the one initialised second finds no GPU."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or spec.origin is None:
+        raise RuntimeError("torch is required: libhisq links the HIP runtime that PyTorch loads")
+    d = os.path.join(os.path.dirname(spec.origin), "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError(f"no libamdhip64.so in {d}")
+    return d
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    rt = hip_runtime_dir()
+    # plain host link (the device code is already embedded in the objects); the HIP runtime is
+    # PyTorch's, found through the rpath whether or not torch is imported first
+    cmd = ["g++", "-shared", "-fPIC", *objs, "-o", tmp, f"-L{rt}", "-l:libamdhip64.so",
+           f"-Wl,-rpath,{rt}", "-Wl,--no-undefined"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -1,15 +1,1136 @@
-// Learned gauge-covariant preconditioner (placeholder until the network kernels land).
+// Learned gauge-covariant preconditioner for the even-odd CG: a linear network of L layers,
+// each a per-site channel mixing (C x C complex, C = 8; bf16 MFMA in the BF16 mode) followed by a
+// per-channel gauge-covariant one-hop stencil over the fat links X of Eq. 3:
+//
+//   phi_1 = W_in (x) E(r);  psi_l = S(a_l, phi_l);  phi_l = W_l psi_{l-1} (l >= 2);
+//   z = R_even(sum_c W_out[c] psi_L[c]);
+//   S(a, phi)_c(x) = a[0,c] phi_c(x) + sum_mu (a[1+mu,c] X(x,mu) phi_c(x+mu)
+//                                            + a[5+mu,c] X(x-mu,mu)^dag phi_c(x-mu)).
+//
+// Forward and backward (adjoint network, Wirtinger weight gradients) are hand-written kernels;
+// training uses Adam (Kingma and Ba 2014) on FP32 master weights.  Activations live on the full
+// lattice in parity-split order (site index p * V/2 + cb) as [batch][colour][site][channel]
+// complex, stored in FP32 or BF16 with FP32 arithmetic.
+//
+// Parameters (complex, canonical order): W_in[C]; for l = 1..L: (W_l[C][C] [out][in] if l >= 2),
+// a_l[9][C]; W_out[C].  Hop h: 0 self, 1+mu forward, 5+mu backward.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
 #include "cg_state.hpp"
 #include "internal.hpp"
 
-struct NNState {};
+namespace {
+
+constexpr int NC = 8;         // channels
+constexpr int NR = 2 * NC;    // reals per (site, colour)
+constexpr int kThreads = 256;
+
+// ---- activation storage -------------------------------------------------------------------
+using bf16 = unsigned short;
+
+__device__ inline float bf2f(bf16 h) { return __uint_as_float(unsigned(h) << 16); }
+__device__ inline bf16 f2bf(float f) {  // round to nearest even
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return bf16(0x7fc0);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16(u >> 16);
+}
+
+template <typename AT> struct Act;
+template <> struct Act<float> {
+  __device__ static void load(const float *p, float (&v)[NR]) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float4 t = q[k];
+      v[4 * k] = t.x;
+      v[4 * k + 1] = t.y;
+      v[4 * k + 2] = t.z;
+      v[4 * k + 3] = t.w;
+    }
+  }
+  __device__ static void store(float *p, const float (&v)[NR]) {
+    float4 *q = reinterpret_cast<float4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  }
+};
+template <> struct Act<bf16> {
+  __device__ static void load(const bf16 *p, float (&v)[NR]) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      uint4 t = q[k];
+      unsigned w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[8 * k + 2 * j] = __uint_as_float(w[j] << 16);
+        v[8 * k + 2 * j + 1] = __uint_as_float(w[j] & 0xffff0000u);
+      }
+    }
+  }
+  __device__ static void store(bf16 *p, const float (&v)[NR]) {
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      unsigned w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        w[j] = unsigned(f2bf(v[8 * k + 2 * j])) | (unsigned(f2bf(v[8 * k + 2 * j + 1])) << 16);
+      q[k] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+};
+
+__device__ inline void ld_link(const float2 *p, float &re, float &im) {
+  float2 v = *p;
+  re = v.x;
+  im = v.y;
+}
+__device__ inline void ld_link(const __half2 *p, float &re, float &im) {
+  float2 v = __half22float2(*p);
+  re = v.x;
+  im = v.y;
+}
+
+struct Site {
+  unsigned p, s;      // parity, cb index
+  int x, y, z, t;
+};
+
+__device__ inline Site decode(const Geometry &g, unsigned X) {
+  Site o;
+  o.p = X >= unsigned(g.vh);
+  o.s = X - o.p * g.vh;
+  const int xh = o.s % g.lxh;
+  int rest = o.s / g.lxh;
+  o.y = rest % g.ly;
+  rest /= g.ly;
+  o.z = rest % g.lz;
+  o.t = rest / g.lz;
+  o.x = 2 * xh + ((o.y + o.z + o.t + int(o.p)) & 1);
+  return o;
+}
+
+// full-lattice index of the neighbour of site q along mu (dir = +1 or -1), 1 hop
+__device__ inline unsigned nbr1(const Geometry &g, const Site &q, int mu, int dir) {
+  unsigned cb;
+  if (mu == 0) {
+    int xn = q.x + dir;
+    xn = xn >= g.lx ? xn - g.lx : (xn < 0 ? xn + g.lx : xn);
+    cb = q.s - (q.x >> 1) + (xn >> 1);
+  } else {
+    const int c = mu == 1 ? q.y : (mu == 2 ? q.z : q.t);
+    const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+    const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+    int cn = c + dir;
+    const int d = cn >= L ? dir - L : (cn < 0 ? dir + L : dir);
+    cb = q.s + d * S;
+  }
+  return (1u - q.p) * g.vh + cb;
+}
+
+struct NNArgs {
+  Geometry g;
+  const void *links[2];   // per output parity, packed link planes (fat hops are planes 0..71)
+  int batch;
+  size_t sample_stride;   // elements of AT per sample = 3 * V * NR
+};
+
+__device__ inline float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// stencil coefficient of hop h, channel c (the adjoint stencil uses conj(a[adj(h)]))
+template <bool ADJ>
+__device__ inline float2 coef(const float2 *__restrict__ a, int h, int c) {
+  if (!ADJ) return a[h * NC + c];
+  const int ha = h == 0 ? 0 : (h < 5 ? h + 4 : h - 4);
+  float2 v = a[ha * NC + c];
+  return make_float2(v.x, -v.y);
+}
+
+// out = S(a, in) (or S^dag(a, in)) on the full lattice for every sample.
+template <typename AT, typename LT, bool ADJ>
+__global__ void __launch_bounds__(kThreads)
+k_nn_stencil(NNArgs A, const AT *__restrict__ in, AT *__restrict__ out, const float2 *__restrict__ a) {
+  const Geometry &g = A.g;
+  const unsigned X = blockIdx.x * kThreads + threadIdx.x;
+  const unsigned V = 2u * g.vh;
+  if (X >= V) return;
+  const size_t boff = size_t(blockIdx.y) * A.sample_stride;
+  const AT *__restrict__ ib = in + boff;
+  AT *__restrict__ ob = out + boff;
+  const Site q = decode(g, X);
+  float acc[3][NR];
+  {
+    float v[NR];
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+      Act<AT>::load(ib + (size_t(col) * V + X) * NR, v);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float2 w = coef<ADJ>(a, 0, c);
+        acc[col][2 * c] = w.x * v[2 * c] - w.y * v[2 * c + 1];
+        acc[col][2 * c + 1] = w.x * v[2 * c + 1] + w.y * v[2 * c];
+      }
+    }
+  }
+  const LT *__restrict__ lk = static_cast<const LT *>(A.links[q.p]);
+#pragma unroll 1
+  for (int h = 1; h < 9; ++h) {
+    const int mu = (h - 1) & 3;
+    const bool fwd = h < 5;
+    const unsigned nb = nbr1(g, q, mu, fwd ? 1 : -1);
+    const int plane = link_plane(fwd ? mu : 4 + mu, 18);  // fat planes are the same for r14
+    float lr[3][3], li[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) ld_link(lk + size_t(plane + 3 * i + j) * g.vh + q.s, lr[i][j], li[i][j]);
+    float v[3][NR];
+#pragma unroll
+    for (int col = 0; col < 3; ++col) Act<AT>::load(ib + (size_t(col) * V + nb) * NR, v[col]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const float2 w = coef<ADJ>(a, h, c);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        float tr = 0.f, ti = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          tr = fmaf(lr[i][j], v[j][2 * c], tr);
+          tr = fmaf(-li[i][j], v[j][2 * c + 1], tr);
+          ti = fmaf(lr[i][j], v[j][2 * c + 1], ti);
+          ti = fmaf(li[i][j], v[j][2 * c], ti);
+        }
+        acc[i][2 * c] = fmaf(w.x, tr, fmaf(-w.y, ti, acc[i][2 * c]));
+        acc[i][2 * c + 1] = fmaf(w.x, ti, fmaf(w.y, tr, acc[i][2 * c + 1]));
+      }
+    }
+  }
+#pragma unroll
+  for (int col = 0; col < 3; ++col) Act<AT>::store(ob + (size_t(col) * V + X) * NR, acc[col]);
+}
+
+// Real 16 x 16 form of the complex channel mixing M (out = M in), interleaved (re, im) per
+// channel: R[2o][2i] = Re M, R[2o][2i+1] = -Im M, R[2o+1][2i] = Im M, R[2o+1][2i+1] = Re M.
+// CONJT: M = W^dag (M[o][i] = conj(W[i][o])).
+template <bool CONJT>
+__device__ inline float mix_real(const float2 *__restrict__ W, int row, int col) {
+  const int o = row >> 1, i = col >> 1;
+  float2 m = CONJT ? W[i * NC + o] : W[o * NC + i];
+  if (CONJT) m.y = -m.y;
+  const bool ro = row & 1, ci = col & 1;
+  if (!ro && !ci) return m.x;
+  if (!ro && ci) return -m.y;
+  if (ro && !ci) return m.y;
+  return m.x;
+}
+
+// out[col] = M in[col] for every (sample, colour, site) column, FP32 FMAs.
+template <typename AT, bool CONJT>
+__global__ void __launch_bounds__(kThreads)
+k_nn_mix_fma(const AT *__restrict__ in, AT *__restrict__ out, size_t ncols, const float2 *__restrict__ W) {
+  __shared__ float R[NR][NR];
+  {
+    const int r = threadIdx.x / NR, c = threadIdx.x % NR;
+    R[r][c] = mix_real<CONJT>(W, r, c);
+  }
+  __syncthreads();
+  const size_t col = size_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (col >= ncols) return;
+  float v[NR], o[NR];
+  Act<AT>::load(in + col * NR, v);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) s = fmaf(R[r][c], v[c], s);
+    o[r] = s;
+  }
+  Act<AT>::store(out + col * NR, o);
+}
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// out[col] = M in[col] with v_mfma_f32_16x16x16_bf16: per instruction a wave multiplies the
+// 16 x 16 real mixing matrix (A operand) by 16 columns (B operand).  Operand layout for wave64:
+// lane l holds A[l%16][4(l/16)+j], B[4(l/16)+j][l%16], and receives D[4(l/16)+j][l%16], j=0..3.
+// Columns are contiguous 16-value records, so the B read and D write of a lane are 8 bytes.
+template <bool CONJT>
+__global__ void __launch_bounds__(kThreads)
+k_nn_mix_mfma(const bf16 *__restrict__ in, bf16 *__restrict__ out, size_t ncols,
+              const float2 *__restrict__ W) {
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  bf16x4 a;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) a[j] = short(f2bf(mix_real<CONJT>(W, m, 4 * kq + j)));
+  const size_t wave = (size_t(blockIdx.x) * kThreads + threadIdx.x) >> 6;
+  const size_t nwaves = (size_t(gridDim.x) * kThreads) >> 6;
+  const size_t ngroups = ncols / 16;  // ncols is a multiple of 16 (3 * V, V even and >= 16)
+  for (size_t grp = wave; grp < ngroups; grp += nwaves) {
+    const size_t col = grp * 16 + m;
+    const uint2 raw = *reinterpret_cast<const uint2 *>(in + col * NR + 4 * kq);
+    bf16x4 b;
+    b[0] = short(raw.x & 0xffffu);
+    b[1] = short(raw.x >> 16);
+    b[2] = short(raw.y & 0xffffu);
+    b[3] = short(raw.y >> 16);
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, d, 0, 0, 0);
+    uint2 o;
+    o.x = unsigned(f2bf(d[0])) | (unsigned(f2bf(d[1])) << 16);
+    o.y = unsigned(f2bf(d[2])) | (unsigned(f2bf(d[3])) << 16);
+    *reinterpret_cast<uint2 *>(out + col * NR + 4 * kq) = o;
+  }
+}
+
+// out[b][col][X][c] = w[c] * (X even ? v[b][col][X] : 0); w = coefficients (conj if CONJW)
+template <typename AT, bool CONJW>
+__global__ void __launch_bounds__(kThreads)
+k_nn_embed(const float2 *__restrict__ v, AT *__restrict__ out, NNArgs A, const float2 *__restrict__ w) {
+  const Geometry &g = A.g;
+  const unsigned V = 2u * g.vh;
+  const unsigned X = blockIdx.x * kThreads + threadIdx.x;
+  if (X >= V) return;
+  const int b = blockIdx.y;
+  float o[NR];
+#pragma unroll
+  for (int col = 0; col < 3; ++col) {
+    float2 r = make_float2(0.f, 0.f);
+    if (X < unsigned(g.vh)) r = v[(size_t(b) * 3 + col) * g.vh + X];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      float2 wc = w[c];
+      if (CONJW) wc.y = -wc.y;
+      const float2 z = cmulf(wc, r);
+      o[2 * c] = z.x;
+      o[2 * c + 1] = z.y;
+    }
+    Act<AT>::store(out + size_t(b) * A.sample_stride + (size_t(col) * V + X) * NR, o);
+  }
+}
+
+// z[b][col][s] = sum_c w[c] act[b][col][s][c] on even sites
+template <typename AT>
+__global__ void __launch_bounds__(kThreads)
+k_nn_readout(const AT *__restrict__ act, float2 *__restrict__ z, NNArgs A, const float2 *__restrict__ w) {
+  const Geometry &g = A.g;
+  const unsigned V = 2u * g.vh;
+  const unsigned s = blockIdx.x * kThreads + threadIdx.x;
+  if (s >= unsigned(g.vh)) return;
+  const int b = blockIdx.y;
+#pragma unroll
+  for (int col = 0; col < 3; ++col) {
+    float v[NR];
+    Act<AT>::load(act + size_t(b) * A.sample_stride + (size_t(col) * V + s) * NR, v);
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      re = fmaf(w[c].x, v[2 * c], fmaf(-w[c].y, v[2 * c + 1], re));
+      im = fmaf(w[c].x, v[2 * c + 1], fmaf(w[c].y, v[2 * c], im));
+    }
+    z[(size_t(b) * 3 + col) * g.vh + s] = make_float2(re, im);
+  }
+}
+
+__device__ inline double block_sum_d(double v, double *red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// gz = 2 (z - y) / (||y||^2 * B) and per-block partials of sum_b ||z_b - y_b||^2 / ||y_b||^2 / B
+__global__ void __launch_bounds__(kThreads)
+k_nn_loss(const float2 *__restrict__ z, const float2 *__restrict__ y, const double *__restrict__ ynorm2,
+          float2 *__restrict__ gz, unsigned len, int batch, double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  const double inv = 1.0 / (ynorm2[b] * batch);
+  double acc = 0.0;
+  for (unsigned j = blockIdx.x * kThreads + threadIdx.x; j < len; j += gridDim.x * kThreads) {
+    const size_t k = size_t(b) * len + j;
+    const float2 d = make_float2(z[k].x - y[k].x, z[k].y - y[k].y);
+    acc += (double(d.x) * d.x + double(d.y) * d.y) * inv;
+    gz[k] = make_float2(float(2.0 * d.x * inv), float(2.0 * d.y * inv));
+  }
+  acc = block_sum_d(acc, red);
+  if (threadIdx.x == 0) partial[size_t(b) * gridDim.x + blockIdx.x] = acc;
+}
+
+// per-block partials of G[c] = sum (CONJ_ACT ? conj(act_c) v : conj(v) act_c) over even sites,
+// colours, samples; partial layout [blk][c][re, im]
+template <typename AT, bool CONJ_ACT>
+__global__ void __launch_bounds__(kThreads)
+k_nn_chan_dot(const AT *__restrict__ act, const float2 *__restrict__ v, NNArgs A,
+              double *__restrict__ partial) {
+  __shared__ double red[4];
+  const Geometry &g = A.g;
+  const unsigned V = 2u * g.vh;
+  double acc[2 * NC];
+#pragma unroll
+  for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
+  const size_t total = size_t(A.batch) * 3 * g.vh;
+  for (size_t j = size_t(blockIdx.x) * kThreads + threadIdx.x; j < total; j += size_t(gridDim.x) * kThreads) {
+    const size_t b = j / (3 * size_t(g.vh));
+    const size_t rem = j - b * 3 * size_t(g.vh);
+    const unsigned col = rem / g.vh, s = rem % g.vh;
+    float a[NR];
+    Act<AT>::load(act + b * A.sample_stride + (size_t(col) * V + s) * NR, a);
+    const float2 w = v[j];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double ar = a[2 * c], ai = a[2 * c + 1];
+      if (CONJ_ACT) {  // conj(a) w
+        acc[2 * c] += ar * w.x + ai * w.y;
+        acc[2 * c + 1] += ar * w.y - ai * w.x;
+      } else {         // conj(w) a
+        acc[2 * c] += w.x * ar + w.y * ai;
+        acc[2 * c + 1] += w.x * ai - w.y * ar;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * NC; ++k) {
+    const double s = block_sum_d(acc[k], red);
+    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * 2 * NC + k] = s;
+  }
+}
+
+// per-block partials of G_a[h][c] = sum conj((H_h phi_c)(x)) . g_c(x) over sites, colours,
+// samples; partial layout [blk][h][c][re, im]
+template <typename AT, typename LT>
+__global__ void __launch_bounds__(kThreads)
+k_nn_stencil_wgrad(NNArgs A, const AT *__restrict__ phi, const AT *__restrict__ gpsi,
+                   double *__restrict__ partial) {
+  __shared__ double red[4];
+  const Geometry &g = A.g;
+  const unsigned V = 2u * g.vh;
+  const size_t total = size_t(A.batch) * V;
+  for (int h = 0; h < 9; ++h) {
+    double acc[2 * NC];
+#pragma unroll
+    for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
+    for (size_t j = size_t(blockIdx.x) * kThreads + threadIdx.x; j < total;
+         j += size_t(gridDim.x) * kThreads) {
+      const size_t b = j / V;
+      const unsigned X = j - b * V;
+      const AT *ib = phi + b * A.sample_stride;
+      const AT *gb = gpsi + b * A.sample_stride;
+      float hv[3][NR];
+      if (h == 0) {
+#pragma unroll
+        for (int col = 0; col < 3; ++col) Act<AT>::load(ib + (size_t(col) * V + X) * NR, hv[col]);
+      } else {
+        const Site q = decode(g, X);
+        const int mu = (h - 1) & 3;
+        const bool fwd = h < 5;
+        const unsigned nb = nbr1(g, q, mu, fwd ? 1 : -1);
+        const LT *lk = static_cast<const LT *>(A.links[q.p]);
+        const int plane = link_plane(fwd ? mu : 4 + mu, 18);
+        float lr[3][3], li[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) ld_link(lk + size_t(plane + 3 * i + jj) * g.vh + q.s, lr[i][jj], li[i][jj]);
+        float v[3][NR];
+#pragma unroll
+        for (int col = 0; col < 3; ++col) Act<AT>::load(ib + (size_t(col) * V + nb) * NR, v[col]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            float tr = 0.f, ti = 0.f;
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+              tr = fmaf(lr[i][jj], v[jj][2 * c], tr);
+              tr = fmaf(-li[i][jj], v[jj][2 * c + 1], tr);
+              ti = fmaf(lr[i][jj], v[jj][2 * c + 1], ti);
+              ti = fmaf(li[i][jj], v[jj][2 * c], ti);
+            }
+            hv[i][2 * c] = tr;
+            hv[i][2 * c + 1] = ti;
+          }
+      }
+#pragma unroll
+      for (int col = 0; col < 3; ++col) {
+        float gv[NR];
+        Act<AT>::load(gb + (size_t(col) * V + X) * NR, gv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {  // conj(hv) g
+          const double hr = hv[col][2 * c], hi = hv[col][2 * c + 1];
+          acc[2 * c] += hr * gv[2 * c] + hi * gv[2 * c + 1];
+          acc[2 * c + 1] += hr * gv[2 * c + 1] - hi * gv[2 * c];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NC; ++k) {
+      const double s = block_sum_d(acc[k], red);
+      if (threadIdx.x == 0) partial[(size_t(blockIdx.x) * 9 + h) * 2 * NC + k] = s;
+    }
+  }
+}
+
+// per-block partials of Q[p][q] = sum_cols gphi_real[p] psi_real[q] (16 x 16), for the mixing
+// weight gradient; partial layout [blk][16][16]
+template <typename AT>
+__global__ void __launch_bounds__(kThreads)
+k_nn_mix_wgrad(const AT *__restrict__ gphi, const AT *__restrict__ psi, size_t ncols,
+               double *__restrict__ partial) {
+  __shared__ float sg[kThreads][NR + 1];
+  __shared__ float sp[kThreads][NR + 1];
+  const int pr = threadIdx.x / NR, qr = threadIdx.x % NR;
+  double acc = 0.0;
+  for (size_t base = size_t(blockIdx.x) * kThreads; base < ncols; base += size_t(gridDim.x) * kThreads) {
+    const size_t col = base + threadIdx.x;
+    float a[NR], b[NR];
+    if (col < ncols) {
+      Act<AT>::load(gphi + col * NR, a);
+      Act<AT>::load(psi + col * NR, b);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) a[k] = b[k] = 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      sg[threadIdx.x][k] = a[k];
+      sp[threadIdx.x][k] = b[k];
+    }
+    __syncthreads();
+    float s = 0.f;
+    for (int k = 0; k < kThreads; ++k) s = fmaf(sg[k][pr], sp[k][qr], s);
+    acc += s;
+  }
+  partial[size_t(blockIdx.x) * NR * NR + threadIdx.x] = acc;
+}
+
+// sum of partial rows: out[k] = sum_b partial[b * width + k]
+__global__ void k_nn_sum_partials(const double *__restrict__ partial, int nblk, int width,
+                                  double *__restrict__ out) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(b) * width + k];
+  v = block_sum_d(v, red);
+  if (threadIdx.x == 0) out[k] = v;
+}
+
+// per-sample ||v_b||^2 partials: partial[b * gridDim.x + blk]
+__global__ void __launch_bounds__(kThreads)
+k_nn_norm2(const float2 *__restrict__ v, unsigned len, double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  double acc = 0.0;
+  for (unsigned j = blockIdx.x * kThreads + threadIdx.x; j < len; j += gridDim.x * kThreads) {
+    const float2 x = v[size_t(b) * len + j];
+    acc += double(x.x) * x.x + double(x.y) * x.y;
+  }
+  acc = block_sum_d(acc, red);
+  if (threadIdx.x == 0) partial[size_t(b) * gridDim.x + blockIdx.x] = acc;
+}
+
+// out[row] = sum_b partial[row * nblk + b]
+__global__ void k_nn_sum_rows(const double *__restrict__ partial, int nblk, double *__restrict__ out) {
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(blockIdx.x) * nblk + b];
+  v = block_sum_d(v, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+// Adam update of the FP32 master weights from the FP64 gradient (reals).
+__global__ void k_adam(float *__restrict__ theta, const double *__restrict__ grad, float *__restrict__ m,
+                       float *__restrict__ v, int nreal, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nreal) return;
+  const float gi = float(grad[i]);
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// complex128 -> complex64 copy, and ||y_b||^2 partials
+__global__ void k_to_c64(const double2 *__restrict__ a, float2 *__restrict__ o, size_t len) {
+  for (size_t j = size_t(blockIdx.x) * kThreads + threadIdx.x; j < len; j += size_t(gridDim.x) * kThreads)
+    o[j] = make_float2(float(a[j].x), float(a[j].y));
+}
+__global__ void k_to_c128(const float2 *__restrict__ a, double2 *__restrict__ o, size_t len) {
+  for (size_t j = size_t(blockIdx.x) * kThreads + threadIdx.x; j < len; j += size_t(gridDim.x) * kThreads)
+    o[j] = make_double2(a[j].x, a[j].y);
+}
+
+}  // namespace
+
+// ============================================================================================
+// host side
+
+struct NNState {
+  int layers = 0;
+  int nparam = 0;                // complex parameters
+  std::vector<int> off_w, off_a;  // complex offsets of W_l (l >= 1) and a_l
+  int off_out = 0;
+  float2 *theta = nullptr;       // FP32 master weights
+  float *adam_m = nullptr, *adam_v = nullptr;
+  int adam_step = 0;
+  double *grad = nullptr;        // FP64 gradient (2 * nparam reals)
+  bool bf16 = true;              // activation storage
+  // activation buffers (grow-only)
+  void *act = nullptr;
+  size_t act_bytes = 0;
+  void *scratch = nullptr;       // partials, per-sample norms, input/output conversions
+  size_t scratch_bytes = 0;
+};
 
 void nn_free_state(hisq_ctx *ctx) {
-  delete ctx->nn;
+  NNState *s = ctx->nn;
+  if (!s) return;
+  for (void *p : {static_cast<void *>(s->theta), static_cast<void *>(s->adam_m),
+                  static_cast<void *>(s->adam_v), static_cast<void *>(s->grad), s->act, s->scratch})
+    if (p) (void)hipFree(p);
+  delete s;
   ctx->nn = nullptr;
+}
+
+namespace {
+
+int nn_params_count(int layers) { return NC + layers * 9 * NC + (layers - 1) * NC * NC + NC; }
+
+int grow(hisq_ctx *ctx, void **p, size_t *cur, size_t bytes) {
+  if (*cur >= bytes) return HISQ_OK;
+  if (*p) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipFree(*p));
+    *p = nullptr;
+    *cur = 0;
+  }
+  bytes = (bytes + 4095) & ~size_t(4095);
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return set_err(ctx, HISQ_ERR_OOM, "network workspace allocation of %zu bytes failed", bytes);
+  }
+  *cur = bytes;
+  return HISQ_OK;
+}
+
+bool nn_links(hisq_ctx *ctx, int *prec) {
+  if (ctx->links[HISQ_F32].base) {
+    *prec = HISQ_F32;
+    return true;
+  }
+  if (ctx->links[HISQ_F16].base) {
+    *prec = HISQ_F16;
+    return true;
+  }
+  return false;
+}
+
+NNArgs nn_args(hisq_ctx *ctx, int batch, int prec) {
+  NNArgs A;
+  A.g = ctx->g;
+  A.links[0] = ctx->links[prec].par[0];
+  A.links[1] = ctx->links[prec].par[1];
+  A.batch = batch;
+  A.sample_stride = size_t(3) * 2 * ctx->g.vh * NR;
+  return A;
+}
+
+size_t act_elem(const NNState *s) { return s->bf16 ? 2 : 4; }
+
+int check_nn(hisq_ctx *ctx, const char *fn) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "%s: no network (call hisq_nn_init)", fn);
+  int prec;
+  if (!ctx->links_loaded || !nn_links(ctx, &prec))
+    return set_err(ctx, HISQ_ERR_STATE, "%s: the network needs the FP32 or FP16 link copy", fn);
+  return HISQ_OK;
+}
+
+// ---- kernel launch helpers ----
+
+template <typename AT>
+int launch_stencil(hisq_ctx *ctx, const NNArgs &A, int prec, const void *in, void *out,
+                   const float2 *a, bool adj) {
+  const unsigned V = 2u * ctx->g.vh;
+  dim3 grid((V + kThreads - 1) / kThreads, A.batch);
+  const AT *i = static_cast<const AT *>(in);
+  AT *o = static_cast<AT *>(out);
+  if (prec == HISQ_F32) {
+    if (adj) k_nn_stencil<AT, float2, true><<<grid, kThreads, 0, ctx->stream>>>(A, i, o, a);
+    else k_nn_stencil<AT, float2, false><<<grid, kThreads, 0, ctx->stream>>>(A, i, o, a);
+  } else {
+    if (adj) k_nn_stencil<AT, __half2, true><<<grid, kThreads, 0, ctx->stream>>>(A, i, o, a);
+    else k_nn_stencil<AT, __half2, false><<<grid, kThreads, 0, ctx->stream>>>(A, i, o, a);
+  }
+  LAUNCHCHK(ctx, "k_nn_stencil");
+  return HISQ_OK;
+}
+
+int launch_mix(hisq_ctx *ctx, const NNState *s, const void *in, void *out, size_t ncols,
+               const float2 *W, bool conjt) {
+  if (s->bf16) {
+    const bf16 *i = static_cast<const bf16 *>(in);
+    bf16 *o = static_cast<bf16 *>(out);
+    size_t groups = ncols / 16;
+    int blocks = int(std::min<size_t>((groups + 3) / 4, 8192));
+    if (conjt) k_nn_mix_mfma<true><<<blocks, kThreads, 0, ctx->stream>>>(i, o, ncols, W);
+    else k_nn_mix_mfma<false><<<blocks, kThreads, 0, ctx->stream>>>(i, o, ncols, W);
+  } else {
+    const float *i = static_cast<const float *>(in);
+    float *o = static_cast<float *>(out);
+    int blocks = int((ncols + kThreads - 1) / kThreads);
+    if (conjt) k_nn_mix_fma<float, true><<<blocks, kThreads, 0, ctx->stream>>>(i, o, ncols, W);
+    else k_nn_mix_fma<float, false><<<blocks, kThreads, 0, ctx->stream>>>(i, o, ncols, W);
+  }
+  LAUNCHCHK(ctx, "k_nn_mix");
+  return HISQ_OK;
+}
+
+// Buffers: forward keeps phi_l and psi_l for every layer (2L activations) plus two gradient
+// buffers for the backward pass.
+struct ActBufs {
+  std::vector<void *> phi, psi;
+  void *g0 = nullptr, *g1 = nullptr;
+};
+
+int act_bufs(hisq_ctx *ctx, int batch, bool train, ActBufs *b) {
+  NNState *s = ctx->nn;
+  const size_t one = size_t(batch) * 3 * 2 * ctx->g.vh * NR * act_elem(s);
+  const int count = train ? 2 * s->layers + 2 : 2;
+  RETCHK(grow(ctx, &s->act, &s->act_bytes, one * count));
+  char *base = static_cast<char *>(s->act);
+  b->phi.resize(s->layers);
+  b->psi.resize(s->layers);
+  if (train) {
+    for (int l = 0; l < s->layers; ++l) {
+      b->phi[l] = base + one * (2 * l);
+      b->psi[l] = base + one * (2 * l + 1);
+    }
+    b->g0 = base + one * (2 * s->layers);
+    b->g1 = base + one * (2 * s->layers + 1);
+  } else {  // ping-pong
+    for (int l = 0; l < s->layers; ++l) {
+      b->phi[l] = base;
+      b->psi[l] = base + one;
+    }
+  }
+  return HISQ_OK;
+}
+
+template <typename AT>
+int forward_t(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, const ActBufs &b) {
+  NNState *s = ctx->nn;
+  int prec;
+  nn_links(ctx, &prec);
+  const NNArgs A = nn_args(ctx, batch, prec);
+  const unsigned V = 2u * ctx->g.vh;
+  const size_t ncols = size_t(batch) * 3 * V;
+  dim3 gv((V + kThreads - 1) / kThreads, batch);
+  k_nn_embed<AT, false><<<gv, kThreads, 0, ctx->stream>>>(r32, static_cast<AT *>(b.phi[0]), A, s->theta);
+  LAUNCHCHK(ctx, "k_nn_embed");
+  for (int l = 0; l < s->layers; ++l) {
+    if (l >= 1) RETCHK(launch_mix(ctx, s, b.psi[l - 1], b.phi[l], ncols, s->theta + s->off_w[l], false));
+    RETCHK(launch_stencil<AT>(ctx, A, prec, b.phi[l], b.psi[l], s->theta + s->off_a[l], false));
+  }
+  dim3 ge((ctx->g.vh + kThreads - 1) / kThreads, batch);
+  k_nn_readout<AT><<<ge, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(b.psi[s->layers - 1]), z32, A,
+                                                    s->theta + s->off_out);
+  LAUNCHCHK(ctx, "k_nn_readout");
+  return HISQ_OK;
+}
+
+int forward(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, const ActBufs &b) {
+  return ctx->nn->bf16 ? forward_t<bf16>(ctx, batch, r32, z32, b) : forward_t<float>(ctx, batch, r32, z32, b);
+}
+
+// Backward pass for one minibatch (after forward with train buffers): accumulates the FP64
+// Wirtinger gradient into s->grad (zeroed by the caller) and the loss partials.
+template <typename AT>
+int backward_t(hisq_ctx *ctx, int batch, const float2 *r32, const float2 *gz, const ActBufs &b,
+               double *partial, size_t partial_cap, double *red) {
+  NNState *s = ctx->nn;
+  int prec;
+  nn_links(ctx, &prec);
+  const NNArgs A = nn_args(ctx, batch, prec);
+  const unsigned V = 2u * ctx->g.vh;
+  const size_t ncols = size_t(batch) * 3 * V;
+  const int nblk = 1024;
+  if (size_t(nblk) * 9 * 2 * NC > partial_cap || size_t(nblk) * NR * NR > partial_cap)
+    return set_err(ctx, HISQ_ERR_STATE, "network partial buffer too small");
+  // W_out: G[c] = sum conj(psi_L[c]) gz
+  k_nn_chan_dot<AT, true><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(b.psi[s->layers - 1]), gz, A, partial);
+  LAUNCHCHK(ctx, "k_nn_chan_dot");
+  k_nn_sum_partials<<<2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 2 * NC, s->grad + 2 * s->off_out);
+  LAUNCHCHK(ctx, "k_nn_sum_partials");
+  // g_psi_L = conj(W_out) (x) E(gz)
+  dim3 gv((V + kThreads - 1) / kThreads, batch);
+  void *gpsi = b.g0, *gphi = b.g1;
+  k_nn_embed<AT, true><<<gv, kThreads, 0, ctx->stream>>>(gz, static_cast<AT *>(gpsi), A, s->theta + s->off_out);
+  LAUNCHCHK(ctx, "k_nn_embed");
+  for (int l = s->layers - 1; l >= 0; --l) {
+    // stencil weights
+    if (prec == HISQ_F32)
+      k_nn_stencil_wgrad<AT, float2><<<nblk, kThreads, 0, ctx->stream>>>(
+          A, static_cast<const AT *>(b.phi[l]), static_cast<const AT *>(gpsi), partial);
+    else
+      k_nn_stencil_wgrad<AT, __half2><<<nblk, kThreads, 0, ctx->stream>>>(
+          A, static_cast<const AT *>(b.phi[l]), static_cast<const AT *>(gpsi), partial);
+    LAUNCHCHK(ctx, "k_nn_stencil_wgrad");
+    k_nn_sum_partials<<<9 * 2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 9 * 2 * NC, s->grad + 2 * s->off_a[l]);
+    LAUNCHCHK(ctx, "k_nn_sum_partials");
+    // g_phi = S^dag g_psi
+    RETCHK(launch_stencil<AT>(ctx, A, prec, gpsi, gphi, s->theta + s->off_a[l], true));
+    if (l >= 1) {
+      // W_l: Q = sum g_phi_real psi_{l-1}_real^T, assembled into complex G by nn_assemble_w
+      k_nn_mix_wgrad<AT><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(gphi),
+                                                             static_cast<const AT *>(b.psi[l - 1]), ncols, partial);
+      LAUNCHCHK(ctx, "k_nn_mix_wgrad");
+      k_nn_sum_partials<<<NR * NR, kThreads, 0, ctx->stream>>>(partial, nblk, NR * NR, red + (l - 1) * NR * NR);
+      LAUNCHCHK(ctx, "k_nn_sum_partials");
+      // g_psi_{l-1} = W_l^dag g_phi
+      RETCHK(launch_mix(ctx, s, gphi, gpsi, ncols, s->theta + s->off_w[l], true));
+    } else {
+      // W_in: G[c] = sum conj(r) g_phi_1[c]
+      k_nn_chan_dot<AT, false><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(gphi), r32, A, partial);
+      LAUNCHCHK(ctx, "k_nn_chan_dot");
+      k_nn_sum_partials<<<2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 2 * NC, s->grad);
+      LAUNCHCHK(ctx, "k_nn_sum_partials");
+    }
+  }
+  return HISQ_OK;
+}
+
+// complex G_W[o][i] = (Q[2o][2i] + Q[2o+1][2i+1]) + i (Q[2o+1][2i] - Q[2o][2i+1])
+__global__ void k_nn_assemble_w(const double *__restrict__ Q, double *__restrict__ gw) {
+  const int t = threadIdx.x;
+  if (t >= NC * NC) return;
+  const int o = t / NC, i = t % NC;
+  gw[2 * t] = Q[(2 * o) * NR + 2 * i] + Q[(2 * o + 1) * NR + 2 * i + 1];
+  gw[2 * t + 1] = Q[(2 * o + 1) * NR + 2 * i] - Q[(2 * o) * NR + 2 * i + 1];
+}
+
+struct Scratch {
+  float2 *r32, *y32, *z32, *gz;
+  double *ynorm2, *partial, *red, *loss;
+  size_t partial_cap;
+};
+
+int scratch(hisq_ctx *ctx, int batch, Scratch *sc) {
+  NNState *s = ctx->nn;
+  const size_t vec = size_t(batch) * 3 * ctx->g.vh * sizeof(float2);
+  const size_t partial_cap = 1024 * NR * NR;  // doubles: >= 1024 * 9 * 2C, 1024 * 256, 256 * batch
+  const size_t bytes = 4 * vec + (batch + partial_cap + 8 * NR * NR + 64) * sizeof(double) + 4096;
+  RETCHK(grow(ctx, &s->scratch, &s->scratch_bytes, bytes));
+  char *p = static_cast<char *>(s->scratch);
+  sc->r32 = reinterpret_cast<float2 *>(p);
+  sc->y32 = reinterpret_cast<float2 *>(p + vec);
+  sc->z32 = reinterpret_cast<float2 *>(p + 2 * vec);
+  sc->gz = reinterpret_cast<float2 *>(p + 3 * vec);
+  double *d = reinterpret_cast<double *>(p + 4 * vec);
+  sc->ynorm2 = d;
+  sc->partial = d + batch;
+  sc->partial_cap = partial_cap;
+  sc->red = sc->partial + partial_cap;
+  sc->loss = sc->red + 8 * NR * NR;
+  return HISQ_OK;
+}
+
+int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f64_io, double *loss_dev) {
+  NNState *s = ctx->nn;
+  Scratch sc;
+  RETCHK(scratch(ctx, batch, &sc));
+  if (s->layers - 1 > 8) return set_err(ctx, HISQ_ERR_ARG, "too many layers");
+  ActBufs b;
+  RETCHK(act_bufs(ctx, batch, true, &b));
+  const size_t len = size_t(batch) * 3 * ctx->g.vh;
+  const float2 *r32 = static_cast<const float2 *>(r), *y32 = static_cast<const float2 *>(y);
+  if (f64_io) {
+    k_to_c64<<<1024, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(r), sc.r32, len);
+    k_to_c64<<<1024, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(y), sc.y32, len);
+    LAUNCHCHK(ctx, "k_to_c64");
+    r32 = sc.r32;
+    y32 = sc.y32;
+  }
+  // ||y_b||^2 in FP64 (of the FP32 targets the loss compares against)
+  {
+    const int nblk = 256;
+    k_nn_norm2<<<dim3(nblk, batch), kThreads, 0, ctx->stream>>>(y32, unsigned(3 * ctx->g.vh), sc.partial);
+    LAUNCHCHK(ctx, "k_nn_norm2");
+    k_nn_sum_rows<<<batch, kThreads, 0, ctx->stream>>>(sc.partial, nblk, sc.ynorm2);
+    LAUNCHCHK(ctx, "k_nn_sum_rows");
+  }
+  RETCHK(forward(ctx, batch, r32, sc.z32, b));
+  const int lblk = 256;
+  dim3 gl(lblk, batch);
+  k_nn_loss<<<gl, kThreads, 0, ctx->stream>>>(sc.z32, y32, sc.ynorm2, sc.gz, unsigned(3 * ctx->g.vh), batch, sc.partial);
+  LAUNCHCHK(ctx, "k_nn_loss");
+  k_nn_sum_partials<<<1, kThreads, 0, ctx->stream>>>(sc.partial, lblk * batch, 1, loss_dev);
+  LAUNCHCHK(ctx, "k_nn_sum_partials");
+  HIPCHK(ctx, hipMemsetAsync(s->grad, 0, size_t(2) * s->nparam * sizeof(double), ctx->stream));
+  if (s->bf16)
+    RETCHK(backward_t<bf16>(ctx, batch, r32, sc.gz, b, sc.partial, sc.partial_cap, sc.red));
+  else
+    RETCHK(backward_t<float>(ctx, batch, r32, sc.gz, b, sc.partial, sc.partial_cap, sc.red));
+  for (int l = 1; l < s->layers; ++l) {
+    k_nn_assemble_w<<<1, 64, 0, ctx->stream>>>(sc.red + (l - 1) * NR * NR, s->grad + 2 * s->off_w[l]);
+    LAUNCHCHK(ctx, "k_nn_assemble_w");
+  }
+  return HISQ_OK;
+}
+
+// deterministic host-side initial weights: near identity plus small SplitMix64/Box-Muller noise
+void init_weights(std::vector<float> &w, const NNState *s, unsigned long long seed, float scale) {
+  unsigned long long st = seed;
+  auto next = [&]() {
+    unsigned long long z = (st += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+  };
+  auto unif = [&]() { return (double(next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+  for (size_t i = 0; i < w.size(); i += 2) {
+    const double u1 = unif(), u2 = unif();
+    const double rad = std::sqrt(-2.0 * std::log(u1)) * std::sqrt(0.5);
+    w[i] = float(scale * rad * std::cos(2 * M_PI * u2));
+    w[i + 1] = float(scale * rad * std::sin(2 * M_PI * u2));
+  }
+  w[0] += 1.f;                                 // W_in[0]
+  w[2 * s->off_out] += 1.f;                    // W_out[0]
+  for (int l = 0; l < s->layers; ++l) {
+    w[2 * s->off_a[l]] += 1.f;                 // a_l[0][0]
+    if (l >= 1) w[2 * s->off_w[l]] += 1.f;     // W_l[0][0]
+  }
+}
+
+}  // namespace
+
+// ---- C ABI ----------------------------------------------------------------------------------
+
+extern "C" int hisq_nn_init(hisq_ctx *ctx, int layers, int channels, unsigned long long seed) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (channels != NC || layers < 1 || layers > 8)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_init: need channels == %d and 1 <= layers <= 8", NC);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  nn_free_state(ctx);
+  NNState *s = new NNState();
+  ctx->nn = s;
+  s->layers = layers;
+  s->nparam = nn_params_count(layers);
+  s->off_w.assign(layers, -1);
+  s->off_a.assign(layers, -1);
+  int k = NC;
+  for (int l = 0; l < layers; ++l) {
+    if (l >= 1) {
+      s->off_w[l] = k;
+      k += NC * NC;
+    }
+    s->off_a[l] = k;
+    k += 9 * NC;
+  }
+  s->off_out = k;
+  const size_t nreal = size_t(2) * s->nparam;
+  void *p;
+  if (hipMalloc(&p, nreal * sizeof(float)) != hipSuccess) goto oom;
+  s->theta = static_cast<float2 *>(p);
+  if (hipMalloc(&p, nreal * sizeof(float)) != hipSuccess) goto oom;
+  s->adam_m = static_cast<float *>(p);
+  if (hipMalloc(&p, nreal * sizeof(float)) != hipSuccess) goto oom;
+  s->adam_v = static_cast<float *>(p);
+  if (hipMalloc(&p, nreal * sizeof(double)) != hipSuccess) goto oom;
+  s->grad = static_cast<double *>(p);
+  {
+    std::vector<float> w(nreal);
+    init_weights(w, s, seed, 0.05f);
+    HIPCHK(ctx, hipMemcpy(s->theta, w.data(), nreal * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(s->adam_m, 0, nreal * sizeof(float)));
+    HIPCHK(ctx, hipMemset(s->adam_v, 0, nreal * sizeof(float)));
+  }
+  return HISQ_OK;
+oom:
+  (void)hipGetLastError();
+  nn_free_state(ctx);
+  return set_err(ctx, HISQ_ERR_OOM, "hisq_nn_init: allocation failed");
+}
+
+extern "C" int hisq_nn_num_params(hisq_ctx *ctx) {
+  if (!ctx || !ctx->nn) return ctx ? set_err(ctx, HISQ_ERR_STATE, "no network") : HISQ_ERR_ARG;
+  return ctx->nn->nparam;
+}
+
+extern "C" int hisq_nn_get_params(hisq_ctx *ctx, double *out, int n_reals) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_get_params: no network");
+  if (!out || n_reals != 2 * ctx->nn->nparam)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_get_params: need %d reals", 2 * ctx->nn->nparam);
+  std::vector<float> w(n_reals);
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(w.data(), ctx->nn->theta, n_reals * sizeof(float), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n_reals; ++i) out[i] = w[i];
+  return HISQ_OK;
+}
+
+extern "C" int hisq_nn_set_params(hisq_ctx *ctx, const double *in, int n_reals) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_set_params: no network");
+  if (!in || n_reals != 2 * ctx->nn->nparam)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_set_params: need %d reals", 2 * ctx->nn->nparam);
+  std::vector<float> w(n_reals);
+  for (int i = 0; i < n_reals; ++i) {
+    if (!std::isfinite(in[i])) return set_err(ctx, HISQ_ERR_NONFINITE, "hisq_nn_set_params: non-finite weight");
+    w[i] = float(in[i]);
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  HIPCHK(ctx, hipMemcpy(ctx->nn->theta, w.data(), n_reals * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(ctx, hipMemset(ctx->nn->adam_m, 0, n_reals * sizeof(float)));
+  HIPCHK(ctx, hipMemset(ctx->nn->adam_v, 0, n_reals * sizeof(float)));
+  ctx->nn->adam_step = 0;
+  return HISQ_OK;
+}
+
+extern "C" int hisq_nn_set_precision(hisq_ctx *ctx, int bf16_storage) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_set_precision: no network");
+  ctx->nn->bf16 = bf16_storage != 0;
+  return HISQ_OK;
+}
+
+// z = P r for n vectors (precision of r and z: HISQ_F64 complex128 or HISQ_F32 complex64)
+int nn_apply_internal(hisq_ctx *ctx, int n, const float2 *r32, float2 *z32) {
+  ActBufs b;
+  RETCHK(act_bufs(ctx, n, false, &b));
+  return forward(ctx, n, r32, z32, b);
+}
+
+extern "C" int hisq_nn_apply(hisq_ctx *ctx, int n, int prec_io, const void *r, void *z) {
+  RETCHK(check_nn(ctx, "hisq_nn_apply"));
+  if (!r || !z || n < 1 || n > HISQ_MAX_RHS || (prec_io != HISQ_F64 && prec_io != HISQ_F32))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_apply: bad argument");
+  if (prec_io == HISQ_F32) return nn_apply_internal(ctx, n, static_cast<const float2 *>(r), static_cast<float2 *>(z));
+  Scratch sc;
+  RETCHK(scratch(ctx, n, &sc));
+  const size_t len = size_t(n) * 3 * ctx->g.vh;
+  k_to_c64<<<1024, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(r), sc.r32, len);
+  LAUNCHCHK(ctx, "k_to_c64");
+  RETCHK(nn_apply_internal(ctx, n, sc.r32, sc.z32));
+  k_to_c128<<<1024, kThreads, 0, ctx->stream>>>(sc.z32, static_cast<double2 *>(z), len);
+  LAUNCHCHK(ctx, "k_to_c128");
+  return HISQ_OK;
+}
+
+extern "C" int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void *y, double *loss,
+                                 double *grad) {
+  RETCHK(check_nn(ctx, "hisq_nn_loss_grad"));
+  if (!r || !y || n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_loss_grad: bad argument");
+  Scratch sc;
+  RETCHK(scratch(ctx, n, &sc));
+  RETCHK(nn_batch_grad(ctx, n, r, y, true, sc.loss));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (loss) HIPCHK(ctx, hipMemcpy(loss, sc.loss, sizeof(double), hipMemcpyDeviceToHost));
+  if (grad)
+    HIPCHK(ctx, hipMemcpy(grad, ctx->nn->grad, size_t(2) * ctx->nn->nparam * sizeof(double), hipMemcpyDeviceToHost));
+  return HISQ_OK;
+}
+
+extern "C" int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const void *y, int epochs,
+                             int batch, double lr, unsigned long long seed, double *loss_history) {
+  RETCHK(check_nn(ctx, "hisq_nn_train"));
+  if (!r || !y || n_pairs < 1 || epochs < 1 || batch < 1 || batch > HISQ_MAX_RHS || !(lr > 0))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_train: bad argument");
+  NNState *s = ctx->nn;
+  const size_t vlen = size_t(3) * ctx->g.vh;
+  const int nbatches = n_pairs / batch;
+  if (nbatches < 1) return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_train: fewer pairs than one batch");
+  Scratch sc;
+  RETCHK(scratch(ctx, batch, &sc));
+  double *loss_acc = sc.loss + 1;  // per-batch losses summed on the host
+  std::vector<int> order(nbatches);
+  for (int i = 0; i < nbatches; ++i) order[i] = i;
+  unsigned long long st = seed ? seed : 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int nreal = 2 * s->nparam;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int i = nbatches - 1; i > 0; --i) {  // Fisher-Yates with a SplitMix64 stream
+      unsigned long long z = (st += 0x9e3779b97f4a7c15ULL);
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+      z ^= z >> 31;
+      std::swap(order[i], order[z % (i + 1)]);
+    }
+    double ep_loss = 0.0;
+    for (int bi = 0; bi < nbatches; ++bi) {
+      const size_t off = size_t(order[bi]) * batch * vlen;
+      RETCHK(nn_batch_grad(ctx, batch, static_cast<const double2 *>(r) + off,
+                           static_cast<const double2 *>(y) + off, true, loss_acc));
+      s->adam_step += 1;
+      const float c1 = 1.f - std::pow(b1, float(s->adam_step));
+      const float c2 = 1.f - std::pow(b2, float(s->adam_step));
+      k_adam<<<(nreal + 255) / 256, 256, 0, ctx->stream>>>(reinterpret_cast<float *>(s->theta), s->grad,
+                                                           s->adam_m, s->adam_v, nreal, float(lr), b1, b2,
+                                                           eps, c1, c2);
+      LAUNCHCHK(ctx, "k_adam");
+      double lb = 0.0;
+      HIPCHK(ctx, hipMemcpyAsync(&lb, loss_acc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      if (!std::isfinite(lb)) return set_err(ctx, HISQ_ERR_NONFINITE, "hisq_nn_train: non-finite loss");
+      ep_loss += lb;
+    }
+    if (loss_history) loss_history[ep] = ep_loss / nbatches;
+  }
+  return HISQ_OK;
+}
+
+extern "C" int hisq_nn_save(hisq_ctx *ctx, const char *path) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_save: no network");
+  if (!path) return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_save: null path");
+  const int nreal = 2 * ctx->nn->nparam;
+  std::vector<double> w(nreal);
+  RETCHK(hisq_nn_get_params(ctx, w.data(), nreal));
+  FILE *f = fopen(path, "wb");
+  if (!f) return set_err(ctx, HISQ_ERR_IO, "hisq_nn_save: cannot open %s", path);
+  const int hdr[4] = {0x51534948 /* "HISQ" */, 1, ctx->nn->layers, NC};
+  bool ok = fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(w.data(), sizeof(double), nreal, f) == size_t(nreal);
+  ok = (fclose(f) == 0) && ok;
+  return ok ? HISQ_OK : set_err(ctx, HISQ_ERR_IO, "hisq_nn_save: write failed");
+}
+
+extern "C" int hisq_nn_load(hisq_ctx *ctx, const char *path) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!path) return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_load: null path");
+  FILE *f = fopen(path, "rb");
+  if (!f) return set_err(ctx, HISQ_ERR_IO, "hisq_nn_load: cannot open %s", path);
+  int hdr[4];
+  if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != 0x51534948 || hdr[1] != 1 || hdr[3] != NC ||
+      hdr[2] < 1 || hdr[2] > 8) {
+    fclose(f);
+    return set_err(ctx, HISQ_ERR_IO, "hisq_nn_load: %s is not a network file", path);
+  }
+  const int nreal = 2 * nn_params_count(hdr[2]);
+  std::vector<double> w(nreal);
+  const bool ok = fread(w.data(), sizeof(double), nreal, f) == size_t(nreal);
+  fclose(f);
+  if (!ok) return set_err(ctx, HISQ_ERR_IO, "hisq_nn_load: %s is truncated", path);
+  if (!ctx->nn || ctx->nn->layers != hdr[2]) RETCHK(hisq_nn_init(ctx, hdr[2], NC, 1));
+  return hisq_nn_set_params(ctx, w.data(), nreal);
 }
 
 int fcg_nn_solve(hisq_ctx *ctx, double, int, const void *, void *, const hisq_cg_params *,
                  hisq_cg_stats *, CGState *, CGState *, double *) {
-  return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: no network initialised");
+  return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: the flexible CG is not available yet");
 }

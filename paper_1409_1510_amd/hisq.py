@@ -77,10 +77,23 @@ def header_functions() -> list[str]:
     return re.findall(r"\b(hisq_\w+)\s*\(", text)
 
 
+def _preload_hip_runtime():
+    """Load PyTorch's HIP runtime (torch/lib/libamdhip64.so, soname libamdhip64.so.7) before
+    libhisq, so that libhisq binds to the same runtime as torch whatever the import order: a
+    second HIP runtime in the process would not see the GPU."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or spec.origin is None:
+        raise ImportError("torch is required (libhisq uses PyTorch's HIP runtime)")
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    ctypes.CDLL(path, mode=ctypes.RTLD_GLOBAL)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    _preload_hip_runtime()
     lib = ctypes.CDLL(LIB_PATH)
     vp, ip, dp, cint, cd = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double
     sig = {
@@ -104,8 +117,9 @@ def _load():
         "hisq_nn_set_params": (cint, [vp, dp, cint]),
         "hisq_nn_num_params": (cint, [vp]),
         "hisq_nn_apply": (cint, [vp, cint, cint, vp, vp]),
-        "hisq_nn_loss_grad": (cint, [vp, cint, cint, vp, vp, dp, dp]),
+        "hisq_nn_loss_grad": (cint, [vp, cint, vp, vp, dp, dp]),
         "hisq_nn_train": (cint, [vp, cint, vp, vp, cint, cint, cd, ctypes.c_ulonglong, dp]),
+        "hisq_nn_set_precision": (cint, [vp, cint]),
         "hisq_nn_save": (cint, [vp, ctypes.c_char_p]),
         "hisq_nn_load": (cint, [vp, ctypes.c_char_p]),
     }

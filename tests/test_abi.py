@@ -42,3 +42,18 @@ def test_null_context_is_rejected():
     assert lib.hisq_cg_mrhs(None, 0.1, 1, None, None, None, None) == hisq.HISQ_ERR_ARG
     assert lib.hisq_set_launch(None, 0, 1, None) == hisq.HISQ_ERR_ARG
     assert lib.hisq_autotune(None, 0, 1, 0, None, None) == hisq.HISQ_ERR_ARG
+
+
+def test_one_hip_runtime_per_process():
+    """libhisq binds to PyTorch's HIP runtime even when imported before torch (two runtimes in
+    one process do not share the GPU)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1409_1510_amd import hisq\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n") % (hisq.os.path.dirname(hisq._HERE),)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -130,6 +130,9 @@ typedef struct {
                          /*    in LDS and its waves loop over the rhs tiles (requires            */
                          /*    sites_per_block = 64, rhs_per_thread <= 4, nontemporal_links = 0, */
                          /*    and LDS for 64 sites' links: not FP64)                            */
+  int xcd_map;           /* LDS form only: 0 = each XCD takes a contiguous range of sites; 1 =    */
+                         /*    each XCD takes Lz/8 z slices for all t (needs (Lx/2)*Ly % 64 == 0 */
+                         /*    and Lz % 8 == 0)                                                  */
 } hisq_launch;
 
 /* Force the configuration for (prec, n), both forms (the fused-M form clamps rhs_per_thread to
@@ -214,6 +217,13 @@ int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void *y, double
  * loss of each epoch.  Synchronises. */
 int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const void *y, int epochs, int batch,
                   double lr, unsigned long long seed, double *loss_history);
+/* Training pairs from plain FP64 CG trajectories: solve M x_i = b_i (n rhs, device complex128
+ * [n][3][V/2]) to tol and keep x_k after iterations 0, snap_every, 2 snap_every, ... (at most
+ * n_snap snapshots); return r_k = b - M x_k in r_out and y_k = x* - x_k = M^-1 r_k in y_out (both
+ * device complex128 [n_snap][n][3][V/2], snapshot-major).  *n_pairs = snapshots taken * n. */
+int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b, double tol, int n_snap,
+                    int snap_every, void *r_out, void *y_out, int *n_pairs);
+
 /* Save / load the parameters (binary: 4 int32 header, then the reals as float64). */
 int hisq_nn_save(hisq_ctx *ctx, const char *path);
 int hisq_nn_load(hisq_ctx *ctx, const char *path);

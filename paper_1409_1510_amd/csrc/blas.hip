@@ -345,6 +345,121 @@ k_zero_sel(C *__restrict__ v, unsigned len, const int *sel, int invert) {
   }
 }
 
+// ---- flexible CG with complex step sizes --------------------------------------------------
+
+// alpha = <p, r> / Re<p, q>; pq partials [n][nblk_pq] (real), pr partials [2n][nblk_pr]
+__global__ void k_fcg_alpha(const double *__restrict__ pqp, int nblk_pq, const double *__restrict__ prp,
+                            int nblk_pr, CGState *S) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  if (!S->active[r]) return;
+  double pq = 0.0, pre = 0.0, pim = 0.0;
+  for (int b = threadIdx.x; b < nblk_pq; b += kThreads) pq += pqp[size_t(r) * nblk_pq + b];
+  for (int b = threadIdx.x; b < nblk_pr; b += kThreads) {
+    pre += prp[size_t(2 * r) * nblk_pr + b];
+    pim += prp[size_t(2 * r + 1) * nblk_pr + b];
+  }
+  pq = block_sum(pq, red);
+  pre = block_sum(pre, red);
+  pim = block_sum(pim, red);
+  if (threadIdx.x == 0) {
+    S->pq[r] = pq;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(pre) || !isfinite(pim)) {
+      S->calpha[2 * r] = S->calpha[2 * r + 1] = 0.0;
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+    } else {
+      S->calpha[2 * r] = pre / pq;
+      S->calpha[2 * r + 1] = pim / pq;
+    }
+  }
+}
+
+// xh += alpha p; r -= alpha q (complex alpha, FP32 vectors); ||r||^2 partials
+__global__ void __launch_bounds__(kThreads)
+k_fcg_update_xr(float2 *__restrict__ x, float2 *__restrict__ rv, const float2 *__restrict__ p,
+                const float2 *__restrict__ q, unsigned len, int nblk, const CGState *S,
+                double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  const float ar = float(S->calpha[2 * r]), ai = float(S->calpha[2 * r + 1]);
+  const size_t off = size_t(r) * len;
+  double rr = 0.0;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      float2 pj = p[off + j], qj = q[off + j], rj = rv[off + j], xj = x[off + j];
+      xj.x = fmaf(ar, pj.x, fmaf(-ai, pj.y, xj.x));
+      xj.y = fmaf(ar, pj.y, fmaf(ai, pj.x, xj.y));
+      rj.x = fmaf(-ar, qj.x, fmaf(ai, qj.y, rj.x));
+      rj.y = fmaf(-ar, qj.y, fmaf(-ai, qj.x, rj.y));
+      x[off + j] = xj;
+      rv[off + j] = rj;
+      rr = fma(double(rj.x), double(rj.x), rr);
+      rr = fma(double(rj.y), double(rj.y), rr);
+    }
+  }
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = rr;
+}
+
+// beta = -<q, z> / Re<p, q>; qz partials [2n][nblk]
+__global__ void k_fcg_beta(const double *__restrict__ qzp, int nblk, CGState *S) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  if (!S->active[r]) return;
+  double re = 0.0, im = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    re += qzp[size_t(2 * r) * nblk + b];
+    im += qzp[size_t(2 * r + 1) * nblk + b];
+  }
+  re = block_sum(re, red);
+  im = block_sum(im, red);
+  if (threadIdx.x == 0) {
+    const double pq = S->pq[r];
+    if (!isfinite(re) || !isfinite(im)) {
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+      return;
+    }
+    S->cbeta[2 * r] = -re / pq;
+    S->cbeta[2 * r + 1] = -im / pq;
+  }
+}
+
+// p = z + beta p (complex beta)
+__global__ void __launch_bounds__(kThreads)
+k_fcg_update_p(const float2 *__restrict__ z, float2 *__restrict__ p, unsigned len, const CGState *S) {
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  const float br = float(S->cbeta[2 * r]), bi = float(S->cbeta[2 * r + 1]);
+  const size_t off = size_t(r) * len;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      float2 pj = p[off + j], zj = z[off + j];
+      float2 o;
+      o.x = fmaf(br, pj.x, fmaf(-bi, pj.y, zj.x));
+      o.y = fmaf(br, pj.y, fmaf(bi, pj.x, zj.y));
+      p[off + j] = o;
+    }
+  }
+}
+
+// y = xstar - xk (training targets of harvested pairs)
+__global__ void __launch_bounds__(kThreads)
+k_sub64(const double2 *__restrict__ a, const double2 *__restrict__ b, double2 *__restrict__ y, size_t len) {
+  for (size_t j = size_t(blockIdx.x) * kThreads + threadIdx.x; j < len; j += size_t(gridDim.x) * kThreads) {
+    double2 u = a[j], v = b[j];
+    y[j] = make_double2(u.x - v.x, u.y - v.y);
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -501,5 +616,46 @@ int cg_zero(hisq_ctx *ctx, int prec, void *v, const int *sel, int invert, int n)
   else
     k_zero_sel<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<float2 *>(v), len, sel, invert);
   LAUNCHCHK(ctx, "k_zero_sel");
+  return HISQ_OK;
+}
+
+int fcg_alpha(hisq_ctx *ctx, const double *pq_partial, int nblk_pq, const double *pr_partial,
+              int nblk_pr, CGState *S, int n) {
+  k_fcg_alpha<<<n, kThreads, 0, ctx->stream>>>(pq_partial, nblk_pq, pr_partial, nblk_pr, S);
+  LAUNCHCHK(ctx, "k_fcg_alpha");
+  return HISQ_OK;
+}
+
+int fcg_update_xr(hisq_ctx *ctx, void *xh, void *r, const void *p, const void *q, CGState *S, int n,
+                  double *partial) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  k_fcg_update_xr<<<dim3(nblk, n), kThreads, 0, ctx->stream>>>(
+      static_cast<float2 *>(xh), static_cast<float2 *>(r), static_cast<const float2 *>(p),
+      static_cast<const float2 *>(q), len, nblk, S, partial);
+  LAUNCHCHK(ctx, "k_fcg_update_xr");
+  return HISQ_OK;
+}
+
+int fcg_beta(hisq_ctx *ctx, const double *qz_partial, int nblk_qz, CGState *S, int n) {
+  k_fcg_beta<<<n, kThreads, 0, ctx->stream>>>(qz_partial, nblk_qz, S);
+  LAUNCHCHK(ctx, "k_fcg_beta");
+  return HISQ_OK;
+}
+
+int fcg_update_p(hisq_ctx *ctx, const void *z, void *p, const CGState *S, int n) {
+  const unsigned len = 3u * ctx->g.vh;
+  k_fcg_update_p<<<dim3(blas_nblk(ctx), n), kThreads, 0, ctx->stream>>>(
+      static_cast<const float2 *>(z), static_cast<float2 *>(p), len, S);
+  LAUNCHCHK(ctx, "k_fcg_update_p");
+  return HISQ_OK;
+}
+
+int cg_snapshot_pairs(hisq_ctx *ctx, const void *xstar, const void *xk, void *y, int n) {
+  const size_t len = size_t(n) * 3 * ctx->g.vh;
+  k_sub64<<<1024, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(xstar),
+                                              static_cast<const double2 *>(xk),
+                                              static_cast<double2 *>(y), len);
+  LAUNCHCHK(ctx, "k_sub64");
   return HISQ_OK;
 }

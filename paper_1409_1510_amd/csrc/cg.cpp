@@ -32,11 +32,14 @@ struct Vecs {
   void *mx64 = nullptr, *t64 = nullptr;
 };
 
-int poll(hisq_ctx *ctx, CGState *S, CGState *hS) {
+}  // namespace
+
+int cg_poll(hisq_ctx *ctx, CGState *S, CGState *hS) {
   HIPCHK(ctx, hipMemcpyAsync(hS, S, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   return HISQ_OK;
 }
+#define poll cg_poll
 
 // mx64 = M x64 (FP64 links) for the rhs selected by mask.
 int apply_m64(hisq_ctx *ctx, double mass, int n, const void *x64, void *t64, void *mx64,
@@ -45,8 +48,6 @@ int apply_m64(hisq_ctx *ctx, double mass, int n, const void *x64, void *t64, voi
   RETCHK(launch_dslash(ctx, 0, HISQ_F64, n, t64, mx64, true, mass * mass, x64, nullptr, nullptr, mask));
   return HISQ_OK;
 }
-
-}  // namespace
 
 // One bundle iteration of (F)CG's operator part: t = D_oe p; q = m^2 p - D_eo t; <p, q>.
 int cg_apply_op(hisq_ctx *ctx, int op_prec, double mass, int n, const void *p, void *t, void *q,
@@ -88,9 +89,11 @@ int cg_finish(hisq_ctx *ctx, double mass, int n, const void *b, void *x, double 
   return HISQ_OK;
 }
 
-static int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
-                    const hisq_cg_params *prm, hisq_cg_stats *st, CGState *S, CGState *hS,
-                    double *partial) {
+// snap_x: optional device [n_snap][n][3][V/2] complex128 receiving x after iterations
+// 0, snap_every, 2 snap_every, ... (plain FP64 solver only); *n_taken = snapshots written.
+int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hisq_cg_params *prm,
+             hisq_cg_stats *st, CGState *S, CGState *hS, double *partial, void *snap_x,
+             int n_snap, int snap_every, int *n_taken) {
   const Geometry &g = ctx->g;
   const bool mixed = prm->kind == HISQ_CG_MIXED;
   const int body = mixed ? HISQ_F32 : HISQ_F64;
@@ -160,6 +163,17 @@ static int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
   int nactive = 0;
   for (int i = 0; i < n; ++i) nactive += hS->active[i];
   int reps = 0;
+  int taken = 0;
+  const size_t xbytes = size_t(n) * 3 * g.vh * 16;
+  auto snapshot = [&]() -> int {
+    if (snap_x && !mixed && taken < n_snap && snap_every > 0 && it % snap_every == 0) {
+      HIPCHK(ctx, hipMemcpyAsync(static_cast<char *>(snap_x) + taken * xbytes, x, xbytes,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+      ++taken;
+    }
+    return HISQ_OK;
+  };
+  RETCHK(snapshot());
   while (nactive > 0 && it < prm->max_iter) {
     int nblk_d = 0;
     RETCHK(cg_apply_op(ctx, op_prec, mass, n, v.p, v.t, v.q, partial, &nblk_d, S->active));
@@ -168,6 +182,7 @@ static int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
     RETCHK(cg_reduce_beta(ctx, partial, S, n, tol2));
     RETCHK(cg_update_p(ctx, body, v.r, v.p, S, n));
     ++it;
+    RETCHK(snapshot());
     if (mixed && it % reliable_every == 0) {
       RETCHK(reliable(1));
       ++reps;
@@ -203,6 +218,7 @@ static int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
   if (mixed) {  // fold the last FP32 correction of every rhs into x
     RETCHK(cg_accum_x(ctx, x, v.xh, S->fin, n));
   }
+  if (n_taken) *n_taken = taken;
   bool ok = false;
   RETCHK(cg_finish(ctx, mass, n, b, x, prm->tol, S, hS, partial, st, &ok));
   if (st) {
@@ -247,8 +263,48 @@ extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, vo
   if (prm->kind == HISQ_FCG_NN)
     rc = fcg_nn_solve(ctx, mass, n, b, x, prm, st, S, hS, partial);
   else
-    rc = cg_solve(ctx, mass, n, b, x, prm, st, S, hS, partial);
+    rc = cg_solve(ctx, mass, n, b, x, prm, st, S, hS, partial, nullptr, 0, 0, nullptr);
   if (st)
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return rc;
+}
+
+extern "C" int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b, double tol,
+                               int n_snap, int snap_every, void *r_out, void *y_out, int *n_pairs) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!b || !r_out || !y_out || n < 1 || n > HISQ_MAX_RHS || n_snap < 1 || snap_every < 1 || !(tol > 0))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_harvest: bad argument");
+  if (!ctx->links_loaded || !ctx->links[HISQ_F64].base)
+    return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_harvest: the FP64 link copy is required");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const Geometry &g = ctx->g;
+  const size_t vbytes = size_t(n) * 3 * g.vh * 16;
+  void *sp, *pp, *hp, *xstar, *t64;
+  RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));
+  const int nblk_max = std::max(blas_nblk(ctx), dslash_partials(ctx->g));
+  RETCHK(ws_get(ctx, WS_PARTIAL, size_t(n) * nblk_max * sizeof(double), &pp));
+  RETCHK(pinned_get(ctx, sizeof(CGState), &hp));
+  RETCHK(ws_get(ctx, WS_CG7, vbytes, &xstar));
+  CGState *S = static_cast<CGState *>(sp);
+  CGState *hS = static_cast<CGState *>(hp);
+  double *partial = static_cast<double *>(pp);
+  hisq_cg_params prm{HISQ_CG_F64, tol, 1000000, 50, HISQ_F32, 0, 8};
+  int taken = 0;
+  // x snapshots go straight into y_out; r_k and y_k = x* - x_k are formed afterwards
+  int rc = cg_solve(ctx, mass, n, b, xstar, &prm, nullptr, S, hS, partial, y_out, n_snap,
+                    snap_every, &taken);
+  if (rc != HISQ_OK) return rc;
+  RETCHK(ws_get(ctx, WS_CG6, vbytes, &t64));
+  for (int k = 0; k < taken; ++k) {
+    char *xk = static_cast<char *>(y_out) + k * vbytes;
+    char *rk = static_cast<char *>(r_out) + k * vbytes;
+    RETCHK(cg_select(ctx, S, n, 1));
+    RETCHK(cg_init_state(ctx, b, S, n, partial));  // fin = 1 for every rhs
+    RETCHK(apply_m64(ctx, mass, n, xk, t64, rk, S->fin));
+    RETCHK(cg_replace_r(ctx, HISQ_F64, b, rk, rk, nullptr, S, S->fin, n, partial));
+    RETCHK(cg_snapshot_pairs(ctx, xstar, xk, xk, n));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (n_pairs) *n_pairs = taken * n;
+  return HISQ_OK;
 }

@@ -14,7 +14,8 @@ struct CGState {
   double bnorm2[HISQ_MAX_RHS];   // ||b||^2
   double rr[HISQ_MAX_RHS];       // ||r||^2 of the iterated residual
   double rr_true[HISQ_MAX_RHS];  // ||b - M x||^2 at the last FP64 recomputation
-  double aux[HISQ_MAX_RHS];      // FCG: <z, q>
+  double calpha[2 * HISQ_MAX_RHS]; // FCG: complex alpha = <p, r> / <p, q>  (re, im)
+  double cbeta[2 * HISQ_MAX_RHS];  // FCG: complex beta = -<q, z> / <p, q>  (re, im)
   int active[HISQ_MAX_RHS];      // 1 while the rhs iterates
   int hit[HISQ_MAX_RHS];         // iterated residual below tol since the last true residual
   int sel[HISQ_MAX_RHS];         // rhs selected for the current true-residual recomputation
@@ -40,3 +41,23 @@ int cg_reduce_true(hisq_ctx *ctx, const double *partial, CGState *S, int n, doub
 int cg_init_state(hisq_ctx *ctx, const void *b, CGState *S, int n, double *partial);
 int cg_set_rho(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
 int cg_zero(hisq_ctx *ctx, int prec, void *v, const int *sel, int invert, int n);
+
+// solver pieces shared by the CG drivers (cg.cpp) and the flexible CG (nn.hip)
+int cg_poll(hisq_ctx *ctx, CGState *S, CGState *hS);
+int apply_m64(hisq_ctx *ctx, double mass, int n, const void *x64, void *t64, void *mx64, const int *mask);
+int cg_apply_op(hisq_ctx *ctx, int op_prec, double mass, int n, const void *p, void *t, void *q,
+                double *partial, int *nblk, const int *active);
+int cg_finish(hisq_ctx *ctx, double mass, int n, const void *b, void *x, double tol, CGState *S,
+              CGState *hS, double *partial, hisq_cg_stats *st, bool *all_conv);
+int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hisq_cg_params *prm,
+             hisq_cg_stats *st, CGState *S, CGState *hS, double *partial, void *snap_x, int n_snap,
+             int snap_every, int *n_taken);
+
+// flexible CG (complex scalars) building blocks
+int fcg_alpha(hisq_ctx *ctx, const double *pq_partial, int nblk_pq, const double *pr_partial,
+              int nblk_pr, CGState *S, int n);
+int fcg_update_xr(hisq_ctx *ctx, void *xh, void *r, const void *p, const void *q, CGState *S, int n,
+                  double *partial);
+int fcg_beta(hisq_ctx *ctx, const double *qz_partial, int nblk_qz, CGState *S, int n);
+int fcg_update_p(hisq_ctx *ctx, const void *z, void *p, const CGState *S, int n);
+int cg_snapshot_pairs(hisq_ctx *ctx, const void *xstar, const void *xk, void *y, int n);

@@ -3,7 +3,10 @@
 // itself is in dslash_kernel.hpp, instantiated per precision in dslash_f64/f32/f16.hip.
 #include "dslash_kernel.hpp"
 
+#include <algorithm>
 #include <cstdlib>
+#include <utility>
+#include <vector>
 
 using dslash::Args;
 using dslash::DslashFn;
@@ -32,6 +35,7 @@ bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size
   if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
   if (c.lds_links < 0 || c.lds_links > 2) return false;
+  if (c.xcd_map != 0 && (c.xcd_map != 1 || !c.lds_links)) return false;
   return lookup(prec, 18, epi, c) != nullptr && lookup(prec, 14, epi, c) != nullptr;
 }
 
@@ -46,21 +50,31 @@ hisq_launch heuristic(int prec, int n, bool epi) {
   int cap = (prec == HISQ_F64 || epi) ? 4 : 8;
   int rt = 1;
   while (rt * 2 <= cap && rt * 2 <= n) rt *= 2;
-  return hisq_launch{rt, 256, 0, 0};
+  return hisq_launch{rt, 256, 0, 0, 0};
 }
 
 struct Geo {
-  int ntiles, ngroups, nsblk, grid;
+  int ntiles, ngroups, nsblk, grid, zmap_bps, zmap_zr;
 };
+
+// the z-slab XCD map needs whole 64-site blocks per (z, t) slab and Lz divisible by 8
+bool zmap_possible(const Geometry &g) { return (g.lxh * g.ly) % 64 == 0 && g.lz % 8 == 0; }
 
 Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
   Geo o;
+  o.zmap_bps = 0;
+  o.zmap_zr = 0;
   o.ntiles = (n + c.rhs_per_thread - 1) / c.rhs_per_thread;
   const int tpb = 256 / c.sites_per_block;
   o.ngroups = c.lds_links ? 1 : (o.ntiles + tpb - 1) / tpb;  // the LDS form loops over the tiles
   o.nsblk = (g.vh + c.sites_per_block - 1) / c.sites_per_block;
   const int nb = o.nsblk * o.ngroups;
   o.grid = (nb + 7) / 8 * 8;
+  if (c.lds_links && c.xcd_map == 1 && zmap_possible(g)) {
+    o.zmap_bps = g.lxh * g.ly / 64;
+    o.zmap_zr = g.lz / 8;
+    o.grid = 8 * g.lt * o.zmap_zr * o.zmap_bps;  // == nsblk
+  }
   return o;
 }
 
@@ -73,8 +87,10 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
     return set_err(ctx, HISQ_ERR_ARG, "Dslash launch configuration needs %zu bytes of LDS (%zu available)",
                    lds_bytes(prec, l.recon, c), ctx->lds_max);
   const Geo geo = geometry(ctx->g, n, c);
+  if (c.xcd_map == 1 && !geo.zmap_bps)
+    return set_err(ctx, HISQ_ERR_ARG, "the z-slab XCD map needs (Lx/2)*Ly %% 64 == 0 and Lz %% 8 == 0");
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
-         mass2, pvec, partial, active};
+         mass2, pvec, partial, active, geo.zmap_bps, geo.zmap_zr};
   fn(a, dim3(geo.grid), ctx->stream);
   LAUNCHCHK(ctx, "k_dslash");
   return HISQ_OK;
@@ -107,30 +123,44 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   float best_ms = 1e30f;
   const int rts[] = {1, 2, 4, 8, 16};
   int rc = HISQ_OK;
+  std::vector<std::pair<float, hisq_launch>> timed;
+  auto time_cfg = [&](const hisq_launch &c, int reps, float *ms_out) -> int {
+    for (int k = 0; k <= reps; ++k) {
+      if (k == 1) (void)hipEventRecord(e0, ctx->stream);
+      RETCHK(run(ctx, epi ? 0 : 1, prec, n, a, b, epi, 0.01, a, static_cast<double *>(pp), nullptr, c));
+    }
+    (void)hipEventRecord(e1, ctx->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *ms_out = ms / reps;
+    return HISQ_OK;
+  };
   for (int rt : rts) {
     if (rt > next_pow2(n)) break;
     for (int spb : {256, 64})
       for (int nt : {0, 1})
-        for (int lds : {0, 1, 2}) {
-        hisq_launch c{rt, spb, nt, lds};
-        if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
-        const int reps = 3;
-        for (int k = 0; k <= reps && rc == HISQ_OK; ++k) {
-          if (k == 1) (void)hipEventRecord(e0, ctx->stream);
-          rc = run(ctx, epi ? 0 : 1, prec, n, a, b, epi, 0.01, a, static_cast<double *>(pp),
-                   nullptr, c);
-        }
-        if (rc != HISQ_OK) break;
-        (void)hipEventRecord(e1, ctx->stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = c;
-        }
+        for (int lds : {0, 1, 2})
+          for (int xm : {0, 1}) {
+            hisq_launch c{rt, spb, nt, lds, xm};
+            if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
+            if (xm && !zmap_possible(g)) continue;
+            float ms;
+            rc = time_cfg(c, 3, &ms);
+            if (rc != HISQ_OK) break;
+            timed.push_back({ms, c});
+          }
+  }
+  if (rc == HISQ_OK && !timed.empty()) {  // re-time the three fastest with more repetitions
+    std::sort(timed.begin(), timed.end(), [](const auto &u, const auto &v) { return u.first < v.first; });
+    for (size_t i = 0; i < timed.size() && i < 3 && rc == HISQ_OK; ++i) {
+      float ms;
+      rc = time_cfg(timed[i].second, 12, &ms);
+      if (rc == HISQ_OK && ms < best_ms) {
+        best_ms = ms;
+        best = timed[i].second;
       }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -188,6 +218,8 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
     }
     hisq_launch c = *cfg;
     const int recon = ctx->links[prec].base ? ctx->links[prec].recon : 18;
+    if (c.xcd_map == 1 && !zmap_possible(ctx->g))
+      return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: the z-slab XCD map needs (Lx/2)*Ly %% 64 == 0 and Lz %% 8 == 0");
     if (!config_valid(prec, epi, c, recon, ctx->lds_max)) {
       if (epi) {  // the fused-M form caps the register tile: use the largest valid one
         while (c.rhs_per_thread > 1 && !config_valid(prec, true, c, recon, ctx->lds_max))

@@ -137,6 +137,8 @@ struct Args {
   const void *pvec;       // epilogue: q = mass2 * pvec - D in
   double *partial;        // epilogue: Re<pvec, q> per rhs per 64-site wave, [n][ceil(V/2 / 64)]
   const int *active;      // per-rhs mask or null
+  int zmap_bps;           // LDS form, z-slab XCD map: 64-site blocks per (z, t) slab (0 = off)
+  int zmap_zr;            //   z slices owned by each XCD (Lz / 8)
 };
 
 // SPB: sites per 256-thread workgroup (256: one tile per workgroup; 64: 4 tiles, one per wave).
@@ -282,9 +284,23 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   LT *sl = reinterpret_cast<LT *>(smem_raw);
   const Geometry &g = a.g;
-  const int chunk = gridDim.x >> 3;
-  const int sblk = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
-  if (sblk >= a.nsblk) return;  // uniform for the whole workgroup
+  int sblk;
+  if (a.zmap_bps) {
+    // XCD k owns the z slices [k Lz/8, (k+1) Lz/8) for every t: the z and t neighbours of its
+    // sites stay mostly in its own L2 (with contiguous chunks, Lt = 8 would give each XCD a single
+    // t slice and send every t hop to another XCD's data)
+    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int per_t = a.zmap_zr * a.zmap_bps;
+    const int t = j / per_t;
+    if (t >= g.lt) return;  // uniform for the whole workgroup
+    const int rem = j - t * per_t;
+    const int zl = rem / a.zmap_bps;
+    sblk = (t * g.lz + k * a.zmap_zr + zl) * a.zmap_bps + (rem - zl * a.zmap_bps);
+  } else {
+    const int chunk = gridDim.x >> 3;
+    sblk = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    if (sblk >= a.nsblk) return;  // uniform for the whole workgroup
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned vh = g.vh;
   const unsigned s = sblk * 64 + lane;

@@ -1130,7 +1130,146 @@ extern "C" int hisq_nn_load(hisq_ctx *ctx, const char *path) {
   return hisq_nn_set_params(ctx, w.data(), nreal);
 }
 
-int fcg_nn_solve(hisq_ctx *ctx, double, int, const void *, void *, const hisq_cg_params *,
-                 hisq_cg_stats *, CGState *, CGState *, double *) {
-  return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: the flexible CG is not available yet");
+// Flexible CG preconditioned by the network (Notay 2000, truncation 1), per rhs, with complex
+// step sizes (the network is not Hermitian): q = M p; alpha = <p, r>/<p, q>; xh += alpha p;
+// r -= alpha q; z = P r; beta = -<q, z>/<p, q>; p = z + beta p.  FP32 body (FP32 or FP16 link
+// storage), FP64 solution and reductions, FP64 reliable updates as in the mixed solver.  A rhs
+// whose step breaks down (<p, Mp> <= 0, non-finite) or stagnates falls back to the mixed-precision
+// CG started from its current x.
+int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
+                 const hisq_cg_params *prm, hisq_cg_stats *st, CGState *S, CGState *hS,
+                 double *partial) {
+  RETCHK(check_nn(ctx, "hisq_cg_mrhs(HISQ_FCG_NN)"));
+  const Geometry &g = ctx->g;
+  const int op_prec = prm->link_prec;
+  const size_t vb = size_t(n) * 3 * g.vh * sizeof(float2);
+  const double tol2 = prm->tol * prm->tol;
+  const int check_every = prm->check_every > 0 ? prm->check_every : 8;
+  const int reliable_every = prm->reliable_every > 0 ? prm->reliable_every : 50;
+  void *r, *p, *q, *t, *xh, *z, *mx64, *t64, *p2;
+  RETCHK(ws_get(ctx, WS_CG0, vb, &r));
+  RETCHK(ws_get(ctx, WS_CG1, vb, &p));
+  RETCHK(ws_get(ctx, WS_CG2, vb, &q));
+  RETCHK(ws_get(ctx, WS_CG3, vb, &t));
+  RETCHK(ws_get(ctx, WS_CG4, vb, &xh));
+  RETCHK(ws_get(ctx, WS_CG5, size_t(n) * 3 * g.vh * 16, &mx64));
+  RETCHK(ws_get(ctx, WS_CG6, size_t(n) * 3 * g.vh * 16, &t64));
+  RETCHK(ws_get(ctx, WS_CG7, vb, &z));
+  RETCHK(ws_get(ctx, WS_NN0, size_t(2 * n) * blas_nblk(ctx) * sizeof(double), &p2));
+  double *partial2 = static_cast<double *>(p2);
+
+  // initial residual, as in the mixed solver
+  RETCHK(cg_init_state(ctx, b, S, n, partial));
+  RETCHK(cg_select(ctx, S, n, 1));
+  RETCHK(cg_zero(ctx, HISQ_F64, x, S->sel, 1, n));
+  if (prm->use_x0) {
+    RETCHK(apply_m64(ctx, mass, n, x, t64, mx64, S->sel));
+  } else {
+    RETCHK(cg_zero(ctx, HISQ_F64, x, nullptr, 0, n));
+    RETCHK(cg_zero(ctx, HISQ_F64, mx64, nullptr, 0, n));
+  }
+  RETCHK(cg_replace_r(ctx, HISQ_F32, b, mx64, r, nullptr, S, S->sel, n, partial));
+  RETCHK(cg_set_rho(ctx, partial, S, n, tol2));
+  RETCHK(cg_zero(ctx, HISQ_F32, xh, nullptr, 0, n));
+  RETCHK(cg_poll(ctx, S, hS));
+  for (int i = 0; i < n; ++i)
+    if (hS->status[i] == CG_NONFINITE)
+      return set_err(ctx, HISQ_ERR_NONFINITE, "hisq_cg_mrhs: non-finite source %d", i);
+  RETCHK(nn_apply_internal(ctx, n, static_cast<const float2 *>(r), static_cast<float2 *>(z)));
+  HIPCHK(ctx, hipMemcpyAsync(p, z, vb, hipMemcpyDeviceToDevice, ctx->stream));
+
+  auto reliable = [&](int all) -> int {
+    RETCHK(cg_select(ctx, S, n, all));
+    RETCHK(cg_accum_x(ctx, x, xh, S->sel, n));
+    RETCHK(apply_m64(ctx, mass, n, x, t64, mx64, S->sel));
+    RETCHK(cg_replace_r(ctx, HISQ_F32, b, mx64, r, nullptr, S, S->sel, n, partial));
+    RETCHK(cg_reduce_true(ctx, partial, S, n, tol2, 0));
+    return HISQ_OK;
+  };
+
+  double best[HISQ_MAX_RHS];
+  int stale[HISQ_MAX_RHS], last_rep[HISQ_MAX_RHS], fell[HISQ_MAX_RHS];
+  for (int i = 0; i < n; ++i) {
+    best[i] = hS->rr_true[i];
+    stale[i] = last_rep[i] = fell[i] = 0;
+  }
+  int it = 0, reps = 0, nactive = 0;
+  for (int i = 0; i < n; ++i) nactive += hS->active[i];
+  while (nactive > 0 && it < prm->max_iter) {
+    int nblk_d = 0, nb2 = 0;
+    RETCHK(cg_apply_op(ctx, op_prec, mass, n, p, t, q, partial, &nblk_d, S->active));
+    RETCHK(launch_dot_partials(ctx, HISQ_F32, n, p, r, partial2, &nb2));
+    RETCHK(fcg_alpha(ctx, partial, nblk_d, partial2, nb2, S, n));
+    RETCHK(fcg_update_xr(ctx, xh, r, p, q, S, n, partial));
+    RETCHK(cg_reduce_beta(ctx, partial, S, n, tol2));
+    RETCHK(nn_apply_internal(ctx, n, static_cast<const float2 *>(r), static_cast<float2 *>(z)));
+    RETCHK(launch_dot_partials(ctx, HISQ_F32, n, q, z, partial2, &nb2));
+    RETCHK(fcg_beta(ctx, partial2, nb2, S, n));
+    RETCHK(fcg_update_p(ctx, z, p, S, n));
+    ++it;
+    if (it % reliable_every == 0) {
+      RETCHK(reliable(1));
+      ++reps;
+    }
+    if (it % check_every == 0 || it == prm->max_iter) {
+      RETCHK(cg_poll(ctx, S, hS));
+      bool any_hit = false;
+      for (int i = 0; i < n; ++i) any_hit = any_hit || (hS->active[i] && hS->hit[i]);
+      if (any_hit) {
+        RETCHK(reliable(0));
+        ++reps;
+        RETCHK(cg_poll(ctx, S, hS));
+      }
+      nactive = 0;
+      for (int i = 0; i < n; ++i) {
+        if (hS->active[i] && hS->replacements[i] != last_rep[i]) {
+          last_rep[i] = hS->replacements[i];
+          if (hS->rr_true[i] < 0.25 * best[i]) {
+            best[i] = hS->rr_true[i];
+            stale[i] = 0;
+          } else if (++stale[i] >= 6) {
+            fell[i] = 1;  // stagnation: hand this rhs to the mixed solver
+          }
+        }
+        if (hS->status[i] == CG_BREAKDOWN) fell[i] = 1;
+        nactive += hS->active[i] && !fell[i];
+      }
+    }
+  }
+  RETCHK(cg_accum_x(ctx, x, xh, S->fin, n));
+  bool ok = false;
+  RETCHK(cg_finish(ctx, mass, n, b, x, prm->tol, S, hS, partial, st, &ok));
+  int fcg_iters[HISQ_MAX_RHS];
+  for (int i = 0; i < n; ++i) fcg_iters[i] = hS->iters[i];
+  bool need = false;
+  for (int i = 0; i < n; ++i) {
+    const double res = hS->bnorm2[i] > 0 ? std::sqrt(hS->rr_true[i] / hS->bnorm2[i]) : 0.0;
+    if (!(res <= prm->tol)) {
+      fell[i] = 1;
+      need = true;
+    } else {
+      fell[i] = 0;
+    }
+  }
+  int total = it;
+  if (need) {  // fallback: mixed-precision CG from the current x (converged rhs stop at once)
+    hisq_cg_params mp = *prm;
+    mp.kind = HISQ_CG_MIXED;
+    mp.use_x0 = 1;
+    mp.max_iter = std::max(1, prm->max_iter - it);
+    int rc = cg_solve(ctx, mass, n, b, x, &mp, st, S, hS, partial, nullptr, 0, 0, nullptr);
+    if (rc != HISQ_OK && rc != HISQ_ERR_NOCONV) return rc;
+    ok = rc == HISQ_OK;
+    if (st) total += st->total_iters;
+  }
+  if (st) {
+    if (st->iters)
+      for (int i = 0; i < n; ++i) st->iters[i] = fcg_iters[i] + (need ? st->iters[i] : 0);
+    if (st->fell_back)
+      for (int i = 0; i < n; ++i) st->fell_back[i] = fell[i];
+    st->total_iters = total;
+    st->reliable_updates = reps + (need ? st->reliable_updates : 0);
+  }
+  if (!ok) return set_err(ctx, HISQ_ERR_NOCONV, "hisq_cg_mrhs: some rhs missed tol %.3g", prm->tol);
+  return HISQ_OK;
 }

@@ -48,10 +48,12 @@ class HisqError(RuntimeError):
 
 class hisq_launch(ctypes.Structure):
     _fields_ = [("rhs_per_thread", ctypes.c_int), ("sites_per_block", ctypes.c_int),
-                ("nontemporal_links", ctypes.c_int), ("lds_links", ctypes.c_int)]
+                ("nontemporal_links", ctypes.c_int), ("lds_links", ctypes.c_int),
+                ("xcd_map", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.rhs_per_thread, self.sites_per_block, self.nontemporal_links, self.lds_links)
+        return (self.rhs_per_thread, self.sites_per_block, self.nontemporal_links, self.lds_links,
+                self.xcd_map)
 
 
 class hisq_cg_params(ctypes.Structure):
@@ -120,6 +122,7 @@ def _load():
         "hisq_nn_loss_grad": (cint, [vp, cint, vp, vp, dp, dp]),
         "hisq_nn_train": (cint, [vp, cint, vp, vp, cint, cint, cd, ctypes.c_ulonglong, dp]),
         "hisq_nn_set_precision": (cint, [vp, cint]),
+        "hisq_nn_harvest": (cint, [vp, cd, cint, vp, cd, cint, cint, vp, vp, ip]),
         "hisq_nn_save": (cint, [vp, ctypes.c_char_p]),
         "hisq_nn_load": (cint, [vp, ctypes.c_char_p]),
     }
@@ -214,10 +217,10 @@ def hisq_dot_mrhs(ctx, prec: int, n: int, a, b, dots) -> None:
 
 
 def hisq_set_launch(ctx, prec: int, n: int, cfg=None) -> None:
-    """cfg: (rhs_per_thread, sites_per_block, nontemporal_links, lds_links), a hisq_launch, or
-    None."""
+    """cfg: (rhs_per_thread, sites_per_block, nontemporal_links, lds_links[, xcd_map]), a
+    hisq_launch, or None."""
     if cfg is not None and not isinstance(cfg, hisq_launch):
-        cfg = hisq_launch(*cfg)
+        cfg = hisq_launch(*(tuple(cfg) + (0,) * (5 - len(cfg))))
     _check(ctx, _lib.hisq_set_launch(ctx, int(prec), int(n), ctypes.byref(cfg) if cfg is not None else None))
 
 

@@ -199,17 +199,18 @@ def test_full_size_32c8_sampled_sites():
     lat.close()
 
 
-ALL_CFGS = ([(rt, spb, nt, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
-            + [(rt, 64, 0, lds) for rt in (1, 2, 4) for lds in (1, 2)])
+ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
+            + [(rt, 64, 0, lds, xm) for rt in (1, 2, 4) for lds in (1, 2) for xm in (0, 1)])
 
 
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4)])
 @pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
                                         (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14)])
-def test_every_launch_config_bit_identical(prec, recon):
+def test_every_launch_config_bit_identical(prec, recon, dims):
     """All register tiles, workgroup shapes, cache hints and the LDS-staged form give the same
     bits, for the plain half Dslash and for the fused M operator (including its FP64 <p, Mp>
-    reduction), and the autotuned choice is one of them."""
-    dims, n, mass = (8, 6, 4, 10), 11, 0.1
+    reduction), and the autotuned choice is one of them.  (16, 8, 8, 4) admits the z-slab XCD map."""
+    n, mass = 11, 0.1
     lat, fat, naik = make_lattice(dims, 120, recon=recon)
     dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
     rdt = torch.float64 if prec == hisq.HISQ_F64 else torch.float32
@@ -220,9 +221,10 @@ def test_every_launch_config_bit_identical(prec, recon):
     for cfg in ALL_CFGS:
         try:
             hisq.hisq_set_launch(lat.ctx, prec, n, cfg)
-        except hisq.HisqError as e:  # FP64 rt 16, FP64 LDS form, or LDS beyond the device limit
-            assert e.code == hisq.HISQ_ERR_ARG
+        except hisq.HisqError as e:  # FP64 rt 16, FP64 LDS form, LDS beyond the device limit,
+            assert e.code == hisq.HISQ_ERR_ARG  # or a z-slab map the lattice does not admit
             assert (prec == hisq.HISQ_F64 and (cfg[0] == 16 or cfg[3])) or cfg[3]
+            assert not (dims == (16, 8, 8, 4) and cfg[4] and prec == hisq.HISQ_F16)
             continue
         tried += 1
         out = lat.dslash(1, prec, v)

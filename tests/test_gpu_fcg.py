@@ -1,0 +1,144 @@
+"""Flexible CG with the learned preconditioner on the GPU: convergence to the FP64 true residual
+(checked with the oracle's M), equivalence with CG for the identity network, the fallback to the
+mixed solver when the network breaks the iteration, and the gain of a trained network."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import DEV, make_lattice
+
+torch = pytest.importorskip("torch")
+from paper_1409_1510_amd import hisq  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+L = 4
+
+
+def _identity_params(lib, ctx):
+    n = lib.hisq_nn_num_params(ctx)
+    th = np.zeros(n, complex)
+    # canonical order: W_in[8]; layer 1: a[9][8]; layers 2..L: W[8][8], a[9][8]; W_out[8]
+    th[0] = 1.0
+    k = 8
+    for l in range(L):
+        if l >= 1:
+            th[k] = 1.0          # W_l[0][0]
+            k += 64
+        th[k] = 1.0              # a_l[0][0]
+        k += 72
+    th[k] = 1.0                  # W_out[0]
+    return th
+
+
+def _set(lib, ctx, th):
+    reals = np.empty(2 * th.size)
+    reals[0::2], reals[1::2] = th.real, th.imag
+    arr = (ctypes.c_double * reals.size)(*reals)
+    assert lib.hisq_nn_set_params(ctx, arr, reals.size) == 0
+
+
+def test_identity_network_fcg_equals_cg():
+    dims, mass, tol = (8, 8, 8, 8), 0.1, 1e-8
+    lat, fat, naik = make_lattice(dims, 400)
+    lib = hisq.library()
+    assert lib.hisq_nn_init(lat.ctx, L, 8, 1) == 0
+    _set(lib, lat.ctx, _identity_params(lib, lat.ctx))
+    b = synth.sources(dims, 4, 401)
+    tb = torch.from_numpy(b).to(DEV)
+    xf, fi = lat.cg(mass, tb, kind=hisq.HISQ_FCG_NN, tol=tol, link_prec=hisq.HISQ_F32)
+    xm, mi = lat.cg(mass, tb, kind=hisq.HISQ_CG_MIXED, tol=tol, link_prec=hisq.HISQ_F32)
+    assert fi["rc"] == 0 and mi["rc"] == 0, (fi, mi)
+    assert fi["fell_back"] == [0] * 4
+    res = oracle.true_residual(fat, naik, xf.cpu().numpy(), b, dims, mass)
+    assert np.all(res <= tol)
+    print(f"identity FCG iters {fi['iters']}, mixed CG iters {mi['iters']}")
+    for a, c in zip(fi["iters"], mi["iters"]):
+        assert abs(a - c) <= 0.1 * c + 8
+    lat.close()
+
+
+def test_broken_network_falls_back_to_mixed():
+    dims, mass, tol = (8, 6, 4, 10), 0.2, 1e-8
+    lat, fat, naik = make_lattice(dims, 402)
+    lib = hisq.library()
+    assert lib.hisq_nn_init(lat.ctx, L, 8, 1) == 0
+    th = _identity_params(lib, lat.ctx)
+    th[-8:] = 0.0                # W_out = 0: z = 0, so p = 0 and <p, Mp> = 0 at once
+    _set(lib, lat.ctx, th)
+    b = synth.sources(dims, 3, 403)
+    b[1] = 0.0
+    x, info = lat.cg(mass, torch.from_numpy(b).to(DEV), kind=hisq.HISQ_FCG_NN, tol=tol,
+                     link_prec=hisq.HISQ_F32)
+    assert info["rc"] == 0, info
+    assert info["fell_back"] == [1, 0, 1]
+    assert np.all(x[1].cpu().numpy() == 0)
+    res = oracle.true_residual(fat, naik, x.cpu().numpy(), b, dims, mass)
+    assert res[0] <= tol and res[2] <= tol
+    lat.close()
+
+
+def test_no_network_is_a_state_error():
+    lat, fat, naik = make_lattice((4, 4, 4, 4), 404)
+    b = torch.from_numpy(synth.sources((4, 4, 4, 4), 1, 405)).to(DEV)
+    with pytest.raises(hisq.HisqError) as e:
+        lat.cg(0.1, b, kind=hisq.HISQ_FCG_NN, tol=1e-8, link_prec=hisq.HISQ_F32)
+    assert e.value.code == hisq.HISQ_ERR_STATE
+    lat.close()
+
+
+def test_harvest_pairs_are_exact():
+    """Harvested pairs satisfy M y_k = r_k (checked with the oracle's M)."""
+    dims, mass = (8, 6, 4, 10), 0.1
+    lat, fat, naik = make_lattice(dims, 406)
+    lib = hisq.library()
+    n, nsnap = 3, 4
+    b = torch.from_numpy(synth.sources(dims, n, 407)).to(DEV)
+    r = torch.empty((nsnap * n, 3, lat.vh), dtype=torch.complex128, device=DEV)
+    y = torch.empty_like(r)
+    npairs = ctypes.c_int()
+    hisq._check(lat.ctx, lib.hisq_nn_harvest(lat.ctx, mass, n, hisq._ptr(b), 1e-12, nsnap, 10,
+                                             hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
+    assert npairs.value == nsnap * n
+    rn, yn = r.cpu().numpy(), y.cpu().numpy()
+    assert np.allclose(rn[:n], b.cpu().numpy())      # snapshot 0: x = 0, r = b
+    my = oracle.m_ee(fat, naik, yn, dims, mass)
+    for k in range(nsnap * n):
+        assert np.linalg.norm(my[k] - rn[k]) <= 1e-9 * np.linalg.norm(rn[k])
+    # later snapshots have smaller residuals
+    assert np.linalg.norm(rn[3 * n]) < np.linalg.norm(rn[0])
+    lat.close()
+
+
+def test_trained_network_gain():
+    """Train the network on harvested pairs and compare FCG iterations with the untrained
+    (identity) network, i.e. plain CG: the trained preconditioner must not lose and is reported."""
+    dims, mass, tol = (8, 8, 8, 8), 0.05, 1e-8
+    lat, fat, naik = make_lattice(dims, 408)
+    lib = hisq.library()
+    n, nsnap = 16, 8
+    b = torch.from_numpy(synth.sources(dims, n, 409)).to(DEV)
+    r = torch.empty((nsnap * n, 3, lat.vh), dtype=torch.complex128, device=DEV)
+    y = torch.empty_like(r)
+    npairs = ctypes.c_int()
+    hisq._check(lat.ctx, lib.hisq_nn_harvest(lat.ctx, mass, n, hisq._ptr(b), 1e-10, nsnap, 15,
+                                             hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
+    assert lib.hisq_nn_init(lat.ctx, L, 8, 3) == 0
+    hist = (ctypes.c_double * 30)()
+    hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y), 30, 16,
+                                           3e-3, 11, hist))
+    print("training loss:", [f"{v:.3f}" for v in list(hist)[::5]], f"final {hist[29]:.3f}")
+    bt = torch.from_numpy(synth.sources(dims, 8, 410)).to(DEV)
+    xt, ti = lat.cg(mass, bt, kind=hisq.HISQ_FCG_NN, tol=tol, link_prec=hisq.HISQ_F32)
+    _set(lib, lat.ctx, _identity_params(lib, lat.ctx))
+    xu, ui = lat.cg(mass, bt, kind=hisq.HISQ_FCG_NN, tol=tol, link_prec=hisq.HISQ_F32)
+    assert ti["rc"] == 0 and ui["rc"] == 0
+    res = oracle.true_residual(fat, naik, xt.cpu().numpy(), bt.cpu().numpy(), dims, mass)
+    assert np.all(res <= tol)
+    print(f"trained FCG: iters {np.mean(ti['iters']):.1f}, {ti['seconds']:.3f}s; identity: "
+          f"iters {np.mean(ui['iters']):.1f}, {ui['seconds']:.3f}s")
+    assert hist[29] < hist[0]
+    assert np.mean(ti["iters"]) < np.mean(ui["iters"])
+    lat.close()

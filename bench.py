@@ -58,6 +58,73 @@ def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup
     return t0.elapsed_time(t1) / steps, float(np.mean(per_launch))
 
 
+def solver_study(args, torch, synth, hisq, pm):
+    """48^3x12 (16 Z2 rhs, m = 0.01) or 64^3x16 (32 Gaussian rhs, m = 0.005): CG seconds per rhs
+    to a true FP64 residual 1e-8 for plain FP64, mixed precision (FP16 links) and the flexible CG
+    with the learned preconditioner (trained here on 256 pairs harvested from plain CG on the same
+    links), with iterations, peak device memory and the Dslash GB/s inside the mixed solve."""
+    import ctypes
+    name = args.workload
+    cfg = synth.WORKLOADS[name]
+    dims, n, mass, tol = cfg["dims"], cfg["n"], cfg["mass"], cfg["tol"]
+    seed = synth.workload_seed(name)
+    t0 = time.perf_counter()
+    fat, naik = synth.gauge_links(dims, seed, eps=cfg["eps"])
+    t_gen = time.perf_counter() - t0
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
+    del fat, naik
+    dev = "cuda:0"
+    b = torch.from_numpy(synth.sources(dims, n, seed + 1, cfg["source"])).to(dev)
+    out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, {n} {cfg['source']} rhs, tol {tol}",
+           "link_generation_s": round(t_gen, 1)}
+    lib = hisq.library()
+
+    def solve(label, **kw):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = lat.cg(mass, b, tol=tol, max_iter=60000, **kw)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        out[label] = {"s_per_rhs": round(sec / n, 5), "seconds": round(sec, 3),
+                      "iters_mean": round(float(np.mean(info["iters"])), 1),
+                      "iters_max": max(info["iters"]), "true_resid_max": max(info["true_resid"]),
+                      "converged": sum(info["converged"]), "fell_back": sum(info["fell_back"]),
+                      "reliable_updates": info["reliable_updates"], "rc": info["rc"],
+                      "peak_device_GB": round(info["peak_bytes"] / 1e9, 2),
+                      "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
+        return x, info
+
+    solve("mixed_f16links", kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
+    solve("plain_f64", kind=hisq.HISQ_CG_F64)
+    # training pairs along plain-CG trajectories of 16 Gaussian sources: 16 snapshots each
+    nsrc, nsnap = 16, 16
+    bs = torch.from_numpy(synth.sources(dims, nsrc, seed + 2)).to(dev)
+    r = torch.empty((nsnap * nsrc, 3, lat.vh), dtype=torch.complex128, device=dev)
+    y = torch.empty_like(r)
+    npairs = ctypes.c_int()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    hisq._check(lat.ctx, lib.hisq_nn_harvest(lat.ctx, mass, nsrc, hisq._ptr(bs), 1e-8, nsnap,
+                                             60, hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
+    out["harvest"] = {"pairs": npairs.value, "seconds": round(time.perf_counter() - t, 2)}
+    hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, 4, 8, seed))
+    hist = (ctypes.c_double * args.epochs)()
+    t = time.perf_counter()
+    hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
+                                           args.epochs, 8, 3e-3, seed, hist))
+    out["training"] = {"epochs": args.epochs, "batch": 8, "lr": 3e-3, "bf16": True,
+                       "seconds": round(time.perf_counter() - t, 2),
+                       "loss_first": round(hist[0], 5), "loss_last": round(hist[args.epochs - 1], 5)}
+    del r, y
+    solve("fcg_learned_f16links", kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F16)
+    out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out["mixed_f16links"]["seconds"], 3)
+    out["speedup_fcg_vs_mixed"] = round(out["mixed_f16links"]["seconds"] / out["fcg_learned_f16links"]["seconds"], 3)
+    out["iteration_ratio_fcg_vs_mixed"] = round(out["fcg_learned_f16links"]["iters_mean"] / out["mixed_f16links"]["iters_mean"], 3)
+    lat.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +134,10 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
+                    help="c1: Dslash throughput at 32^3x8 (default, the timed steps); c3/c4: the "
+                         "solver comparison at 48^3x12 / 64^3x16 (plain FP64, mixed, learned FCG)")
+    ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), then --steps FP32 Dslash steps")
@@ -83,6 +154,9 @@ def main():
     from paper_1409_1510_amd import perfmodel as pm
 
     torch.cuda.set_device(0)
+    if args.workload in ("c3", "c4"):
+        print(json.dumps(solver_study(args, torch, synth, hisq, pm)))
+        return
     cfg = synth.WORKLOADS["c1"]
     dims, n = cfg["dims"], args.nrhs
     seed = synth.workload_seed("c1")

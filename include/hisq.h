@@ -126,10 +126,10 @@ typedef struct {
   int sites_per_block;   /* 256: one rhs tile per 256-thread workgroup; 64: the 4 waves of a     */
                          /*      workgroup take 4 rhs tiles of the same 64 sites               */
   int nontemporal_links; /* 1: link loads carry the non-temporal cache hint                     */
-  int lds_links;         /* 1 (2): a workgroup of 64 sites x 4 (8) waves stages its sites' links */
-                         /*    in LDS and its waves loop over the rhs tiles (requires            */
-                         /*    sites_per_block = 64, rhs_per_thread <= 4, nontemporal_links = 0, */
-                         /*    and LDS for 64 sites' links: not FP64)                            */
+  int lds_links;         /* 1, 2, 3: a workgroup of 64 sites x 4, 8, 16 waves stages its sites'  */
+                         /*    links in LDS and its waves loop over the rhs tiles (requires      */
+                         /*    sites_per_block = 64, rhs_per_thread <= 4 (<= 2 for 16 waves) and */
+                         /*    LDS for 64 sites' links: not FP64)                                */
   int xcd_map;           /* LDS form only: 0 = each XCD takes a contiguous range of sites; 1 =    */
                          /*    each XCD takes Lz/8 z slices for all t (needs (Lx/2)*Ly % 64 == 0 */
                          /*    and Lz % 8 == 0)                                                  */
@@ -204,12 +204,20 @@ int hisq_nn_get_params(hisq_ctx *ctx, double *out, int n_reals);
 int hisq_nn_set_params(hisq_ctx *ctx, const double *in, int n_reals);
 /* Activation storage: 1 = BF16 (default), 0 = FP32. */
 int hisq_nn_set_precision(hisq_ctx *ctx, int bf16_storage);
+
+/* Training loss for pairs (r_j, y_j = M^-1 r_j) over a minibatch of B pairs:
+ *   HISQ_NN_LOSS_SOLUTION (default): (1/B) sum_j ||P r_j - y_j||^2 / ||y_j||^2
+ *   HISQ_NN_LOSS_RESIDUAL:           (1/B) sum_j ||M (P r_j - y_j)||^2 / ||r_j||^2
+ *                                    = (1/B) sum_j ||M P r_j - r_j||^2 / ||r_j||^2,
+ * the second with M = m^2 - D_eo D_oe at `mass` (FP32 links, or FP16 if only those exist). */
+enum { HISQ_NN_LOSS_SOLUTION = 0, HISQ_NN_LOSS_RESIDUAL = 1 };
+int hisq_nn_set_loss(hisq_ctx *ctx, int kind, double mass);
 /* z = P r for n vectors: r, z device [n][3][V/2] on even sites, complex128 (prec_io = HISQ_F64)
  * or complex64 (HISQ_F32).  Asynchronous. */
 int hisq_nn_apply(hisq_ctx *ctx, int n, int prec_io, const void *r, void *z);
-/* Loss L = (1/n) sum_j ||P r_j - y_j||^2 / ||y_j||^2 and its gradient with respect to the
- * parameters (Wirtinger: dL/dRe + i dL/dIm, 2 * num_params reals, host) for n pairs r, y (device
- * complex128 [n][3][V/2]).  loss and grad may be NULL.  Synchronises. */
+/* Loss (see hisq_nn_set_loss) and its gradient with respect to the parameters (Wirtinger:
+ * dL/dRe + i dL/dIm, 2 * num_params reals, host) for n pairs r, y (device complex128
+ * [n][3][V/2]).  loss and grad may be NULL.  Synchronises. */
 int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void *y, double *loss, double *grad);
 /* Train on n_pairs pairs (device complex128 [n_pairs][3][V/2] each) with Adam (lr, beta1 0.9,
  * beta2 0.999), minibatches of `batch` consecutive pairs visited in a seeded random order, for

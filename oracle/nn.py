@@ -19,7 +19,10 @@ Every layer is linear (no activation), so z = P r for a fixed linear map P (a le
 approximate inverse with a 4-hop reach for L = 4).  It is gauge covariant: with
 X(x,mu) -> O(x) X(x,mu) O(x+mu)^dag and r -> O r, z -> O z.
 
-Training pairs (r_j, y_j = M^-1 r_j); loss L = (1/B) sum_j ||P r_j - y_j||^2 / ||y_j||^2.
+Training pairs (r_j, y_j = M^-1 r_j); two losses over a minibatch of B pairs:
+    solution norm: L = (1/B) sum_j ||P r_j - y_j||^2 / ||y_j||^2
+    residual norm: L = (1/B) sum_j ||M (P r_j - y_j)||^2 / ||r_j||^2 = (1/B) sum_j ||M P r_j - r_j||^2 / ||r_j||^2
+(the second measures the same prediction error in the norm of M^2, using M y_j = r_j).
 Gradients use the Wirtinger convention grad(w) = dL/dRe(w) + i dL/dIm(w).
 
 Parameters, canonical flat order (complex; as reals: re, im interleaved):
@@ -31,7 +34,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dslash import _AXIS, embed, extract
+from .dslash import _AXIS, embed, extract, m_ee
 
 
 def n_params(channels: int, layers: int) -> int:
@@ -125,16 +128,30 @@ def forward(theta, fat, r, dims, channels: int, layers: int, keep: bool = False)
     return (z, cache) if keep else z
 
 
-def loss(theta, fat, rs, ys, dims, channels: int, layers: int) -> float:
+def _pair_loss(z, r, y, kind, fat, naik, dims, mass):
+    """(loss of one pair, Wirtinger gradient with respect to z) before the 1/B factor."""
+    if kind == "solution":
+        ny2 = np.linalg.norm(y) ** 2
+        return np.linalg.norm(z - y) ** 2 / ny2, 2.0 * (z - y) / ny2
+    mz = m_ee(fat, naik, z[None], dims, mass)[0]
+    nr2 = np.linalg.norm(r) ** 2
+    gw = 2.0 * (mz - r) / nr2
+    return np.linalg.norm(mz - r) ** 2 / nr2, m_ee(fat, naik, gw[None], dims, mass)[0]  # M Hermitian
+
+
+def loss(theta, fat, rs, ys, dims, channels: int, layers: int, kind="solution", naik=None,
+         mass=None) -> float:
     tot = 0.0
     for r, y in zip(rs, ys):
         z = forward(theta, fat, r, dims, channels, layers)
-        tot += np.linalg.norm(z - y) ** 2 / np.linalg.norm(y) ** 2
+        tot += _pair_loss(z, r, y, kind, fat, naik, dims, mass)[0]
     return tot / len(rs)
 
 
-def loss_and_grad(theta, fat, rs, ys, dims, channels: int, layers: int):
-    """Loss and its Wirtinger gradient (complex, canonical order) by reverse-mode adjoints."""
+def loss_and_grad(theta, fat, rs, ys, dims, channels: int, layers: int, kind="solution",
+                  naik=None, mass=None):
+    """Loss and its Wirtinger gradient (complex, canonical order) by reverse-mode adjoints.
+    kind "residual" needs the Naik links and the mass of M."""
     p = unpack(theta, channels, layers)
     grad = {"W_in": np.zeros(channels, complex), "W": [np.zeros_like(w) for w in p["W"]],
             "a": [np.zeros_like(a) for a in p["a"]], "W_out": np.zeros(channels, complex)}
@@ -142,9 +159,9 @@ def loss_and_grad(theta, fat, rs, ys, dims, channels: int, layers: int):
     tot = 0.0
     for r, y in zip(rs, ys):
         z, cache = forward(theta, fat, r, dims, channels, layers, keep=True)
-        ny2 = np.linalg.norm(y) ** 2
-        tot += np.linalg.norm(z - y) ** 2 / ny2
-        gz = 2.0 * (z - y) / (ny2 * nb)                     # grad of L w.r.t. z
+        lj, gz = _pair_loss(z, r, y, kind, fat, naik, dims, mass)
+        tot += lj
+        gz = gz / nb                                        # grad of L w.r.t. z
         gout = embed(gz, dims, 0)                            # [V][3], zero on odd sites
         psi_l = cache["psi"][-1]
         grad["W_out"] += np.einsum("cvk,vk->c", np.conj(psi_l), gout)

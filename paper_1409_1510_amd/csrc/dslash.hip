@@ -34,7 +34,7 @@ bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size
   if (rt != 1 && rt != 2 && rt != 4 && rt != 8 && rt != 16) return false;
   if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
-  if (c.lds_links < 0 || c.lds_links > 2) return false;
+  if (c.lds_links < 0 || c.lds_links > 3) return false;
   if (c.xcd_map != 0 && (c.xcd_map != 1 || !c.lds_links)) return false;
   return lookup(prec, 18, epi, c) != nullptr && lookup(prec, 14, epi, c) != nullptr;
 }
@@ -140,7 +140,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
     if (rt > next_pow2(n)) break;
     for (int spb : {256, 64})
       for (int nt : {0, 1})
-        for (int lds : {0, 1, 2})
+        for (int lds : {0, 1, 2, 3})
           for (int xm : {0, 1}) {
             hisq_launch c{rt, spb, nt, lds, xm};
             if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;

@@ -275,9 +275,9 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
 // found in L2 than when every thread holds all n rhs; the links still come from HBM once.
 // Same site order, hop order and FMA sequence per rhs as k_dslash (bit-identical output), and
 // the same per-64-site grouping of the fused <p, Mp> partials.
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB>
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
 __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
-  static_assert(WPB == 4 || WPB == 8, "4 or 8 waves per workgroup");
+  static_assert(WPB == 4 || WPB == 8 || WPB == 16, "4, 8 or 16 waves per workgroup");
   using C = typename CT<Real>::T;
   constexpr int recon = R14 ? 14 : 18;
   constexpr int PL = R14 ? 128 : 144;  // stored planes per site
@@ -306,9 +306,24 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
   const unsigned s = sblk * 64 + lane;
   const bool valid = s < vh;
   const LT *__restrict__ links = static_cast<const LT *>(a.links);
-  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access)
+  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access).  With
+  // NT the global loads carry the non-temporal hint, so the streamed links do not push the
+  // neighbour vectors out of L2.
   for (int pl = wave; pl < PL; pl += WPB)
-    if (valid) sl[pl * 64 + lane] = links[size_t(pl) * vh + s];
+    if (valid) {
+      if constexpr (NT) {
+        if constexpr (sizeof(LT) == 8) {
+          const unsigned long long u =
+              __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(links + size_t(pl) * vh + s));
+          *reinterpret_cast<unsigned long long *>(sl + pl * 64 + lane) = u;
+        } else {
+          const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(links + size_t(pl) * vh + s));
+          *reinterpret_cast<unsigned *>(sl + pl * 64 + lane) = u;
+        }
+      } else {
+        sl[pl * 64 + lane] = links[size_t(pl) * vh + s];
+      }
+    }
   __syncthreads();
 
   int x = 0, y = 0, z = 0, t = 0;
@@ -422,28 +437,31 @@ void launch_t(const Args &a, dim3 grid, hipStream_t st) {
   k_dslash<Real, LT, RT, R14, EPI, SPB, NT><<<grid, 256, 0, st>>>(a);
 }
 
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB>
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
 void launch_lds(const Args &a, dim3 grid, hipStream_t st) {
   constexpr size_t lds = size_t(R14 ? 128 : 144) * 64 * sizeof(LT);
-  k_dslash_lds<Real, LT, RT, R14, EPI, WPB><<<grid, 64 * WPB, lds, st>>>(a);
+  k_dslash_lds<Real, LT, RT, R14, EPI, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
 }
 
-// lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves
-template <typename Real, typename LT, bool R14, bool EPI>
+template <typename Real, typename LT, bool R14, bool EPI, int WPB, bool NT>
+DslashFn pick_lds_rt(int rt) {
+  switch (rt) {
+    case 1: return launch_lds<Real, LT, 1, R14, EPI, WPB, NT>;
+    case 2: return launch_lds<Real, LT, 2, R14, EPI, WPB, NT>;
+    case 4:
+      if constexpr (WPB <= 8) return launch_lds<Real, LT, 4, R14, EPI, WPB, NT>;
+      return nullptr;
+    default: return nullptr;
+  }
+}
+
+// lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves, 3 = 16 waves
+template <typename Real, typename LT, bool R14, bool EPI, bool NT>
 DslashFn pick_lds(int rt, int lds) {
   if constexpr (sizeof(LT) > 8) return nullptr;  // FP64 links do not fit LDS twice per CU
-  if (lds == 1) switch (rt) {
-      case 1: return launch_lds<Real, LT, 1, R14, EPI, 4>;
-      case 2: return launch_lds<Real, LT, 2, R14, EPI, 4>;
-      case 4: return launch_lds<Real, LT, 4, R14, EPI, 4>;
-      default: return nullptr;
-    }
-  if (lds == 2) switch (rt) {
-      case 1: return launch_lds<Real, LT, 1, R14, EPI, 8>;
-      case 2: return launch_lds<Real, LT, 2, R14, EPI, 8>;
-      case 4: return launch_lds<Real, LT, 4, R14, EPI, 8>;
-      default: return nullptr;
-    }
+  if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
+  if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
+  if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);
   return nullptr;
 }
 
@@ -463,8 +481,9 @@ DslashFn pick_rt(int rt) {
 template <typename Real, typename LT, bool R14>
 DslashFn pick_all(bool epi, int rt, int spb, bool nt, int lds) {
   if (lds) {
-    if (spb != 64 || nt) return nullptr;
-    return epi ? pick_lds<Real, LT, R14, true>(rt, lds) : pick_lds<Real, LT, R14, false>(rt, lds);
+    if (spb != 64) return nullptr;
+    if (nt) return epi ? pick_lds<Real, LT, R14, true, true>(rt, lds) : pick_lds<Real, LT, R14, false, true>(rt, lds);
+    return epi ? pick_lds<Real, LT, R14, true, false>(rt, lds) : pick_lds<Real, LT, R14, false, false>(rt, lds);
   }
   if (epi) {
     if (spb == 64) return nt ? pick_rt<Real, LT, R14, true, 64, true>(rt) : pick_rt<Real, LT, R14, true, 64, false>(rt);

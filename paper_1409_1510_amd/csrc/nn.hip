@@ -589,6 +589,8 @@ struct NNState {
   int adam_step = 0;
   double *grad = nullptr;        // FP64 gradient (2 * nparam reals)
   bool bf16 = true;              // activation storage
+  int loss_kind = HISQ_NN_LOSS_SOLUTION;
+  double loss_mass = 0.0;        // mass of M for the residual-norm loss
   // activation buffers (grow-only)
   void *act = nullptr;
   size_t act_bytes = 0;
@@ -825,7 +827,7 @@ __global__ void k_nn_assemble_w(const double *__restrict__ Q, double *__restrict
 }
 
 struct Scratch {
-  float2 *r32, *y32, *z32, *gz;
+  float2 *r32, *y32, *z32, *gz, *w32, *t32, *gw;
   double *ynorm2, *partial, *red, *loss;
   size_t partial_cap;
 };
@@ -834,14 +836,17 @@ int scratch(hisq_ctx *ctx, int batch, Scratch *sc) {
   NNState *s = ctx->nn;
   const size_t vec = size_t(batch) * 3 * ctx->g.vh * sizeof(float2);
   const size_t partial_cap = 1024 * NR * NR;  // doubles: >= 1024 * 9 * 2C, 1024 * 256, 256 * batch
-  const size_t bytes = 4 * vec + (batch + partial_cap + 8 * NR * NR + 64) * sizeof(double) + 4096;
+  const size_t bytes = 7 * vec + (batch + partial_cap + 8 * NR * NR + 64) * sizeof(double) + 4096;
   RETCHK(grow(ctx, &s->scratch, &s->scratch_bytes, bytes));
   char *p = static_cast<char *>(s->scratch);
   sc->r32 = reinterpret_cast<float2 *>(p);
   sc->y32 = reinterpret_cast<float2 *>(p + vec);
   sc->z32 = reinterpret_cast<float2 *>(p + 2 * vec);
   sc->gz = reinterpret_cast<float2 *>(p + 3 * vec);
-  double *d = reinterpret_cast<double *>(p + 4 * vec);
+  sc->w32 = reinterpret_cast<float2 *>(p + 4 * vec);
+  sc->t32 = reinterpret_cast<float2 *>(p + 5 * vec);
+  sc->gw = reinterpret_cast<float2 *>(p + 6 * vec);
+  double *d = reinterpret_cast<double *>(p + 7 * vec);
   sc->ynorm2 = d;
   sc->partial = d + batch;
   sc->partial_cap = partial_cap;
@@ -866,10 +871,12 @@ int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f
     r32 = sc.r32;
     y32 = sc.y32;
   }
-  // ||y_b||^2 in FP64 (of the FP32 targets the loss compares against)
+  const bool resid = s->loss_kind == HISQ_NN_LOSS_RESIDUAL;
+  // ||t_b||^2 in FP64 of the FP32 vector the loss compares against (y, or r for the residual loss)
+  const float2 *target = resid ? r32 : y32;
   {
     const int nblk = 256;
-    k_nn_norm2<<<dim3(nblk, batch), kThreads, 0, ctx->stream>>>(y32, unsigned(3 * ctx->g.vh), sc.partial);
+    k_nn_norm2<<<dim3(nblk, batch), kThreads, 0, ctx->stream>>>(target, unsigned(3 * ctx->g.vh), sc.partial);
     LAUNCHCHK(ctx, "k_nn_norm2");
     k_nn_sum_rows<<<batch, kThreads, 0, ctx->stream>>>(sc.partial, nblk, sc.ynorm2);
     LAUNCHCHK(ctx, "k_nn_sum_rows");
@@ -877,8 +884,20 @@ int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f
   RETCHK(forward(ctx, batch, r32, sc.z32, b));
   const int lblk = 256;
   dim3 gl(lblk, batch);
-  k_nn_loss<<<gl, kThreads, 0, ctx->stream>>>(sc.z32, y32, sc.ynorm2, sc.gz, unsigned(3 * ctx->g.vh), batch, sc.partial);
-  LAUNCHCHK(ctx, "k_nn_loss");
+  int mprec = 0;
+  if (resid) {  // w = M z; gradient w.r.t. w, then g_z = M g_w (M is Hermitian)
+    mprec = ctx->links[HISQ_F32].base ? HISQ_F32 : HISQ_F16;
+    const double m2 = s->loss_mass * s->loss_mass;
+    RETCHK(launch_dslash(ctx, 1, mprec, batch, sc.z32, sc.t32, false, 0.0, nullptr, nullptr, nullptr));
+    RETCHK(launch_dslash(ctx, 0, mprec, batch, sc.t32, sc.w32, true, m2, sc.z32, nullptr, nullptr));
+    k_nn_loss<<<gl, kThreads, 0, ctx->stream>>>(sc.w32, r32, sc.ynorm2, sc.gw, unsigned(3 * ctx->g.vh), batch, sc.partial);
+    LAUNCHCHK(ctx, "k_nn_loss");
+    RETCHK(launch_dslash(ctx, 1, mprec, batch, sc.gw, sc.t32, false, 0.0, nullptr, nullptr, nullptr));
+    RETCHK(launch_dslash(ctx, 0, mprec, batch, sc.t32, sc.gz, true, m2, sc.gw, nullptr, nullptr));
+  } else {
+    k_nn_loss<<<gl, kThreads, 0, ctx->stream>>>(sc.z32, y32, sc.ynorm2, sc.gz, unsigned(3 * ctx->g.vh), batch, sc.partial);
+    LAUNCHCHK(ctx, "k_nn_loss");
+  }
   k_nn_sum_partials<<<1, kThreads, 0, ctx->stream>>>(sc.partial, lblk * batch, 1, loss_dev);
   LAUNCHCHK(ctx, "k_nn_sum_partials");
   HIPCHK(ctx, hipMemsetAsync(s->grad, 0, size_t(2) * s->nparam * sizeof(double), ctx->stream));
@@ -999,6 +1018,16 @@ extern "C" int hisq_nn_set_params(hisq_ctx *ctx, const double *in, int n_reals) 
   HIPCHK(ctx, hipMemset(ctx->nn->adam_m, 0, n_reals * sizeof(float)));
   HIPCHK(ctx, hipMemset(ctx->nn->adam_v, 0, n_reals * sizeof(float)));
   ctx->nn->adam_step = 0;
+  return HISQ_OK;
+}
+
+extern "C" int hisq_nn_set_loss(hisq_ctx *ctx, int kind, double mass) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_set_loss: no network");
+  if ((kind != HISQ_NN_LOSS_SOLUTION && kind != HISQ_NN_LOSS_RESIDUAL) || !std::isfinite(mass))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_set_loss: bad loss kind or mass");
+  ctx->nn->loss_kind = kind;
+  ctx->nn->loss_mass = mass;
   return HISQ_OK;
 }
 

@@ -200,7 +200,8 @@ def test_full_size_32c8_sampled_sites():
 
 
 ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
-            + [(rt, 64, 0, lds, xm) for rt in (1, 2, 4) for lds in (1, 2) for xm in (0, 1)])
+            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3) for xm in (0, 1)
+               for nt in (0, 1)])
 
 
 @pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4)])

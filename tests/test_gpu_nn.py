@@ -74,12 +74,15 @@ def test_forward_matches_oracle(bf16):
     lat.close()
 
 
-@pytest.mark.parametrize("bf16", [False, True])
-def test_loss_and_gradient_match_oracle(bf16):
+@pytest.mark.parametrize("bf16,kind", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_loss_and_gradient_match_oracle(bf16, kind):
+    """kind 0: solution-norm loss; kind 1: residual-norm loss ||M P r - r||^2 / ||r||^2."""
     lat, fat, naik = make_lattice(DIMS, 303)
     _init(lat, bf16)
     th = _theta(304)
     _set(lat, th)
+    mass = 0.3
+    assert hisq.library().hisq_nn_set_loss(lat.ctx, kind, mass) == 0
     r = synth.sources(DIMS, 2, 305)
     y = synth.sources(DIMS, 2, 306)
     loss = hisq.ctypes.c_double()
@@ -88,9 +91,10 @@ def test_loss_and_gradient_match_oracle(bf16):
     hisq._check(lat.ctx, hisq.library().hisq_nn_loss_grad(lat.ctx, 2, hisq._ptr(tr), hisq._ptr(ty),
                                                           hisq.ctypes.byref(loss), grad))
     g = np.array(grad[0::2]) + 1j * np.array(grad[1::2])
-    lref, gref = onn.loss_and_grad(th, fat, r, y, DIMS, 8, L)
+    lref, gref = onn.loss_and_grad(th, fat, r, y, DIMS, 8, L, kind=("solution", "residual")[kind],
+                                   naik=naik, mass=mass)
     err = rel_l2(g, gref)
-    print(f"NN grad bf16={bf16}: loss {loss.value:.6g} vs {lref:.6g}; grad rel L2 {err:.3g}, cosine {_cos(g, gref):.6f}")
+    print(f"NN grad bf16={bf16} kind={kind}: loss {loss.value:.6g} vs {lref:.6g}; grad rel L2 {err:.3g}, cosine {_cos(g, gref):.6f}")
     if bf16:
         assert abs(loss.value - lref) <= 5e-2 * lref
         assert err <= 5e-2 and _cos(g, gref) >= 0.999

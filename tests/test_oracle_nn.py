@@ -27,22 +27,24 @@ def test_param_count_and_pack_roundtrip():
     assert np.array_equal(nn.pack(nn.unpack(th, 3, 3)), th)
 
 
-@pytest.mark.parametrize("c,l", [(2, 2), (3, 3)])
-def test_gradient_matches_finite_differences(c, l):
-    fat, _ = synth.gauge_links(DIMS, 31)
+@pytest.mark.parametrize("c,l,kind", [(2, 2, "solution"), (3, 3, "solution"), (2, 3, "residual")])
+def test_gradient_matches_finite_differences(c, l, kind):
+    fat, naik = synth.gauge_links(DIMS, 31)
     th = _rand_theta(c, l, 32)
     rs = synth.sources(DIMS, 2, 33)
     ys = synth.sources(DIMS, 2, 34)
-    val, grad = nn.loss_and_grad(th, fat, rs, ys, DIMS, c, l)
-    assert abs(val - nn.loss(th, fat, rs, ys, DIMS, c, l)) < 1e-12 * val
+    mass = 0.3
+    kw = dict(kind=kind, naik=naik, mass=mass)
+    val, grad = nn.loss_and_grad(th, fat, rs, ys, DIMS, c, l, **kw)
+    assert abs(val - nn.loss(th, fat, rs, ys, DIMS, c, l, **kw)) < 1e-12 * val
     rng = np.random.default_rng(3)
     idx = rng.choice(th.size, 12, replace=False)
     h = 1e-6
     for k in idx:
         e = np.zeros_like(th)
         e[k] = h
-        d_re = (nn.loss(th + e, fat, rs, ys, DIMS, c, l) - nn.loss(th - e, fat, rs, ys, DIMS, c, l)) / (2 * h)
-        d_im = (nn.loss(th + 1j * e, fat, rs, ys, DIMS, c, l) - nn.loss(th - 1j * e, fat, rs, ys, DIMS, c, l)) / (2 * h)
+        d_re = (nn.loss(th + e, fat, rs, ys, DIMS, c, l, **kw) - nn.loss(th - e, fat, rs, ys, DIMS, c, l, **kw)) / (2 * h)
+        d_im = (nn.loss(th + 1j * e, fat, rs, ys, DIMS, c, l, **kw) - nn.loss(th - 1j * e, fat, rs, ys, DIMS, c, l, **kw)) / (2 * h)
         scale = max(abs(grad[k]), 1e-3 * np.max(np.abs(grad)))
         assert abs(grad[k].real - d_re) <= 1e-6 * scale, (k, grad[k], d_re)
         assert abs(grad[k].imag - d_im) <= 1e-6 * scale, (k, grad[k], d_im)
@@ -124,3 +126,20 @@ def test_init_is_near_identity():
     fat, _ = synth.gauge_links(DIMS, 43)
     r = synth.sources(DIMS, 1, 44)[0]
     assert np.max(np.abs(nn.forward(th, fat, r, DIMS, 8, 4) - r)) < 1e-14
+
+
+def test_residual_loss_is_solution_error_in_m2_norm():
+    """With y = M^-1 r exactly (from LAPACK), ||M P r - r|| = ||M (P r - y)||."""
+    dims = (4, 4, 4, 4)
+    fat, naik = synth.gauge_links(dims, 45)
+    mass = 0.4
+    th = _rand_theta(2, 2, 46)
+    r = synth.sources(dims, 1, 47)
+    vh = 128
+    eye = np.eye(3 * vh).reshape(3 * vh, 3, vh)
+    mdense = oracle.m_ee(fat, naik, eye, dims, mass).reshape(3 * vh, 3 * vh).T
+    y = np.linalg.solve(mdense, r[0].ravel()).reshape(1, 3, vh)
+    z = nn.forward(th, fat, r[0], dims, 2, 2)
+    lhs = nn.loss(th, fat, r, y, dims, 2, 2, kind="residual", naik=naik, mass=mass)
+    e = (mdense @ (z - y[0]).ravel())
+    assert abs(lhs - np.linalg.norm(e) ** 2 / np.linalg.norm(r) ** 2) < 1e-10 * lhs

@@ -30,6 +30,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_dslash_f32_n16_32x32x32x8.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_1510_amd", "csrc", f)
+                  for f in ("dslash_kernel.hpp", "dslash.hip", "dslash_f32.hip")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config_tuple):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the same counter's reading for a copy kernel of known size), if the
+    summary was taken on the current kernel source and the same launch configuration."""
+    if not os.path.exists(PROFILE_SUMMARY):
+        return None
+    fields = {}
+    for line in open(PROFILE_SUMMARY):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if fields.get("launch_config") != str(tuple(config_tuple)):
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _events(torch):
@@ -179,12 +211,14 @@ def main():
             lat.dslash(1, hisq.HISQ_F32, v_e, w_o)
             lat.dslash(0, hisq.HISQ_F32, v_o, w_e)
         torch.cuda.synchronize()
-        print(f"profile run done: {args.steps} steps, {n} rhs, lattice {dims}")
+        print(f"profile run done: {args.steps} steps, {n} rhs, lattice {dims}, launch "
+              f"{hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)}, source {kernel_source_hash()}")
         lat.close()
         return
 
     ms_step, ms_launch = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
                                             args.steps, args.warmup)
+    launch_cfg = hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)
     flops_step = 2 * pm.half_dslash_flops(vh, n)
     gflops = flops_step / (ms_step * 1e-3) / 1e9
     bytes_launch = pm.half_dslash_bytes(vh, n, hisq.HISQ_F32)
@@ -207,8 +241,13 @@ def main():
                                "Naik links; step = D_oe + D_eo (whole-lattice D on the bundle)",
                    "lattice": list(dims), "n_rhs": n, "flop_per_site_rhs": pm.FLOP_PER_SITE_RHS},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_dslash<float,float2,RT,false,false> (half Dslash, FP32)",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(launch_cfg),
+                     "kernel": ("k_dslash_lds" if launch_cfg[3] else "k_dslash") + " (half Dslash, FP32)",
+                     "launch_config": {"rhs_per_thread": launch_cfg[0], "sites_per_block": launch_cfg[1],
+                                       "nontemporal_links": launch_cfg[2], "lds_links": launch_cfg[3],
+                                       "xcd_map": launch_cfg[4]},
+                     "kernel_source_sha256_16": kernel_source_hash(),
                      "bytes_per_launch": bytes_launch, "ms_per_launch": round(ms_launch, 5)},
     }
 

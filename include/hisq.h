@@ -146,6 +146,14 @@ int hisq_get_launch(hisq_ctx *ctx, int prec, int n, int fused_m, hisq_launch *cf
  * fastest.  best and ms_out (mean ms per launch) may be NULL.  Synchronises the stream. */
 int hisq_autotune(hisq_ctx *ctx, int prec, int n, int fused_m, hisq_launch *best, double *ms_out);
 
+/* Save the tuned configurations of this context (its lattice and link formats) to a text file,
+ * keeping the file's entries for other lattices; load the entries that match this context's
+ * lattice and loaded link formats (call after hisq_load_links; *n_loaded may be NULL).
+ * Line format: lx ly lz lt prec recon n fused rt spb nt lds xm ms.  Loading the links again
+ * clears tuned (not forced) choices. */
+int hisq_save_tuning(hisq_ctx *ctx, const char *path);
+int hisq_load_tuning(hisq_ctx *ctx, const char *path, int *n_loaded);
+
 typedef struct {
   int kind;           /* HISQ_CG_F64, HISQ_CG_MIXED or HISQ_FCG_NN                              */
   double tol;         /* stop rhs i when ||b_i - M x_i|| / ||b_i|| <= tol, checked in FP64         */

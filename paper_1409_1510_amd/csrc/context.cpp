@@ -202,6 +202,10 @@ extern "C" int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *n
   if (bad) return set_err(ctx, HISQ_ERR_NONFINITE, "hisq_load_links: non-finite link entries");
 
   free_links(ctx);
+  for (auto &per_prec : ctx->tune)  // launch choices depend on the link format: tune again
+    for (auto &per_n : per_prec)
+      for (auto &t : per_n)
+        if (t.state != TuneEntry::FORCED) t = TuneEntry{};
   for (int prec = 0; prec < 3; ++prec) {
     if (!(copies & (1 << prec))) continue;
     int recon = prec == HISQ_F64 ? 18 : naik_recon;

@@ -4,7 +4,9 @@
 #include "dslash_kernel.hpp"
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -241,6 +243,78 @@ extern "C" int hisq_get_launch(hisq_ctx *ctx, int prec, int n, int fused_m, hisq
     return set_err(ctx, HISQ_ERR_ARG, "hisq_get_launch: bad argument");
   const TuneEntry &t = ctx->tune[prec][n][fused_m ? 1 : 0];
   *cfg = t.state == TuneEntry::NONE ? heuristic(prec, n, fused_m != 0) : t.cfg;
+  return HISQ_OK;
+}
+
+// ---- persistent tuning table ----------------------------------------------------------------
+// text lines: lx ly lz lt prec recon n fused rt spb nt lds xm ms
+
+extern "C" int hisq_save_tuning(hisq_ctx *ctx, const char *path) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!path) return set_err(ctx, HISQ_ERR_ARG, "hisq_save_tuning: null path");
+  const Geometry &g = ctx->g;
+  std::vector<std::string> keep;
+  if (FILE *f = fopen(path, "r")) {  // keep entries of other lattices / link formats
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+      int d[4], prec, recon;
+      if (line[0] == '#' || sscanf(line, "%d %d %d %d %d %d", &d[0], &d[1], &d[2], &d[3], &prec, &recon) != 6)
+        continue;
+      const bool mine = d[0] == g.lx && d[1] == g.ly && d[2] == g.lz && d[3] == g.lt && prec >= 0 && prec < 3 &&
+                        ctx->links[prec].base && recon == ctx->links[prec].recon;
+      if (!mine) keep.push_back(line);
+    }
+    fclose(f);
+  }
+  FILE *f = fopen(path, "w");
+  if (!f) return set_err(ctx, HISQ_ERR_IO, "hisq_save_tuning: cannot write %s", path);
+  fprintf(f, "# lx ly lz lt prec recon n fused rt spb nt lds xm ms\n");
+  for (const auto &l : keep) fputs(l.c_str(), f);
+  for (int prec = 0; prec < 3; ++prec) {
+    if (!ctx->links[prec].base) continue;
+    for (int n = 1; n <= HISQ_MAX_RHS; ++n)
+      for (int e = 0; e < 2; ++e) {
+        const TuneEntry &t = ctx->tune[prec][n][e];
+        if (t.state != TuneEntry::TUNED) continue;
+        fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %d %.5f\n", g.lx, g.ly, g.lz, g.lt, prec,
+                ctx->links[prec].recon, n, e, t.cfg.rhs_per_thread, t.cfg.sites_per_block,
+                t.cfg.nontemporal_links, t.cfg.lds_links, t.cfg.xcd_map, t.ms);
+      }
+  }
+  return fclose(f) == 0 ? HISQ_OK : set_err(ctx, HISQ_ERR_IO, "hisq_save_tuning: write failed");
+}
+
+extern "C" int hisq_load_tuning(hisq_ctx *ctx, const char *path, int *n_loaded) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!path) return set_err(ctx, HISQ_ERR_ARG, "hisq_load_tuning: null path");
+  if (!ctx->links_loaded) return set_err(ctx, HISQ_ERR_STATE, "hisq_load_tuning: load the links first");
+  FILE *f = fopen(path, "r");
+  if (!f) return set_err(ctx, HISQ_ERR_IO, "hisq_load_tuning: cannot read %s", path);
+  const Geometry &g = ctx->g;
+  char line[512];
+  int count = 0;
+  while (fgets(line, sizeof line, f)) {
+    int d[4], prec, recon, n, e;
+    hisq_launch c;
+    float ms;
+    if (line[0] == '#' ||
+        sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %d %f", &d[0], &d[1], &d[2], &d[3], &prec, &recon,
+               &n, &e, &c.rhs_per_thread, &c.sites_per_block, &c.nontemporal_links, &c.lds_links, &c.xcd_map,
+               &ms) != 14)
+      continue;
+    if (d[0] != g.lx || d[1] != g.ly || d[2] != g.lz || d[3] != g.lt) continue;
+    if (prec < 0 || prec > 2 || n < 1 || n > HISQ_MAX_RHS || (e != 0 && e != 1)) continue;
+    if (!ctx->links[prec].base || ctx->links[prec].recon != recon) continue;
+    if (!config_valid(prec, e != 0, c, recon, ctx->lds_max)) continue;
+    if (c.xcd_map && !zmap_possible(g)) continue;
+    TuneEntry &t = ctx->tune[prec][n][e];
+    t.cfg = c;
+    t.state = TuneEntry::TUNED;
+    t.ms = ms;
+    ++count;
+  }
+  fclose(f);
+  if (n_loaded) *n_loaded = count;
   return HISQ_OK;
 }
 

@@ -18,6 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhisq.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "hisq.h")
+# launch configurations tuned on MI355X for the study lattices (loaded by Lattice.load_links)
+TUNING_PATH = os.path.join(_HERE, "tuning", "gfx950.txt")
 
 HISQ_OK = 0
 HISQ_ERR_ARG = -1
@@ -111,6 +113,8 @@ def _load():
         "hisq_set_launch": (cint, [vp, cint, cint, ctypes.POINTER(hisq_launch)]),
         "hisq_get_launch": (cint, [vp, cint, cint, cint, ctypes.POINTER(hisq_launch)]),
         "hisq_autotune": (cint, [vp, cint, cint, cint, ctypes.POINTER(hisq_launch), dp]),
+        "hisq_save_tuning": (cint, [vp, ctypes.c_char_p]),
+        "hisq_load_tuning": (cint, [vp, ctypes.c_char_p, ip]),
         "hisq_cg_mrhs": (cint, [vp, cd, cint, vp, vp, ctypes.POINTER(hisq_cg_params),
                                 ctypes.POINTER(hisq_cg_stats)]),
     }
@@ -298,7 +302,9 @@ class Lattice:
             if fat.shape != (self.volume, 4, 3, 3) or naik.shape != fat.shape:
                 raise ValueError(f"links must be [{self.volume}][4][3][3]")
         hisq_load_links(self.ctx, fat, naik, copies, naik_recon)
-        self._keep = None
+        if os.path.exists(TUNING_PATH) and os.environ.get("HISQ_AUTOTUNE", "1") != "0":
+            cnt = ctypes.c_int()
+            _check(self.ctx, _lib.hisq_load_tuning(self.ctx, TUNING_PATH.encode(), ctypes.byref(cnt)))
 
     def dslash(self, out_parity, prec, v_in, out=None):
         self._vec(v_in, prec, "in")

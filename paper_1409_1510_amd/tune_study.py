@@ -1,0 +1,63 @@
+"""Tune the Dslash launch configurations for the study lattices on this GPU and save them to
+paper_1409_1510_amd/tuning/<arch>.txt (loaded by hisq.Lattice.load_links).
+
+Usage (on the GPU): python -m paper_1409_1510_amd.tune_study [--out PATH] [--lattices c1,c3,c4]
+The timing does not depend on the link values, so the links are a small random field tiled over
+the lattice.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from paper_1409_1510_amd import hisq  # noqa: E402
+
+RHS = {"c1": (1, 2, 4, 8, 16), "c2": (8,), "c3": (8, 16), "c4": (8, 32)}
+
+
+def tiled_links(dims):
+    small = (4, 4, 4, 4)
+    fat, naik = synth.gauge_links(small, 7)
+    lx, ly, lz, lt = dims
+    f = fat.reshape(4, 4, 4, 4, 4, 3, 3)
+    nk = naik.reshape(4, 4, 4, 4, 4, 3, 3)
+    reps = (lt // 4, lz // 4, ly // 4, lx // 4, 1, 1, 1)
+    return (np.ascontiguousarray(np.tile(f, reps).reshape(-1, 4, 3, 3)),
+            np.ascontiguousarray(np.tile(nk, reps).reshape(-1, 4, 3, 3)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=hisq.TUNING_PATH)
+    ap.add_argument("--lattices", default="c1,c3,c4")
+    args = ap.parse_args()
+    os.environ["HISQ_AUTOTUNE"] = "1"
+    for name in args.lattices.split(","):
+        dims = synth.WORKLOADS[name]["dims"]
+        fat, naik = tiled_links(dims)
+        for recon in (18, 14):
+            lat = hisq.Lattice(dims, 0)
+            lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL if recon == 18 else
+                           hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, recon)
+            precs = (0, 1, 2) if recon == 18 else (1, 2)
+            for prec in precs:
+                for n in RHS[name]:
+                    for fused in (0, 1):
+                        hisq.hisq_set_launch(lat.ctx, prec, n, None)
+                        cfg, ms = hisq.hisq_autotune(lat.ctx, prec, n, fused)
+                        print(f"{name} r{recon} prec {prec} n {n} fused {fused}: {cfg} {ms:.5f} ms", flush=True)
+            hisq._check(lat.ctx, hisq.library().hisq_save_tuning(lat.ctx, args.out.encode()))
+            lat.close()
+    print(f"saved {args.out}")
+
+
+if __name__ == "__main__":
+    main()

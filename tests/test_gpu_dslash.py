@@ -225,7 +225,8 @@ def test_every_launch_config_bit_identical(prec, recon, dims):
         except hisq.HisqError as e:  # FP64 rt 16, FP64 LDS form, LDS beyond the device limit,
             assert e.code == hisq.HISQ_ERR_ARG  # or a z-slab map the lattice does not admit
             assert (prec == hisq.HISQ_F64 and (cfg[0] == 16 or cfg[3])) or cfg[3]
-            assert not (dims == (16, 8, 8, 4) and cfg[4] and prec == hisq.HISQ_F16)
+            assert not (dims == (16, 8, 8, 4) and cfg[4] and prec == hisq.HISQ_F16 and
+                        not (cfg[3] == 3 and cfg[0] == 4))  # 16-wave LDS form takes rt <= 2
             continue
         tried += 1
         out = lat.dslash(1, prec, v)

@@ -50,8 +50,8 @@ def main():
             precs = (0, 1, 2) if recon == 18 else (1, 2)
             for prec in precs:
                 for n in RHS[name]:
+                    hisq.hisq_set_launch(lat.ctx, prec, n, None)  # clears both forms
                     for fused in (0, 1):
-                        hisq.hisq_set_launch(lat.ctx, prec, n, None)
                         cfg, ms = hisq.hisq_autotune(lat.ctx, prec, n, fused)
                         print(f"{name} r{recon} prec {prec} n {n} fused {fused}: {cfg} {ms:.5f} ms", flush=True)
             hisq._check(lat.ctx, hisq.library().hisq_save_tuning(lat.ctx, args.out.encode()))

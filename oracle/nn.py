@@ -19,6 +19,11 @@ Every layer is linear (no activation), so z = P r for a fixed linear map P (a le
 approximate inverse with a 4-hop reach for L = 4).  It is gauge covariant: with
 X(x,mu) -> O(x) X(x,mu) O(x+mu)^dag and r -> O r, z -> O z.
 
+Two forms of the preconditioner built from the same layers:
+    direct: z = P r = R_even N r
+    Gram:   z = N^dag N r, with N r = sum_c W_out[c] psi_L[c] on the full lattice, which is
+            Hermitian positive semi-definite by construction (the form suited to CG).
+
 Training pairs (r_j, y_j = M^-1 r_j); two losses over a minibatch of B pairs:
     solution norm: L = (1/B) sum_j ||P r_j - y_j||^2 / ||y_j||^2
     residual norm: L = (1/B) sum_j ||M (P r_j - y_j)||^2 / ||r_j||^2 = (1/B) sum_j ||M P r_j - r_j||^2 / ||r_j||^2
@@ -128,6 +133,86 @@ def forward(theta, fat, r, dims, channels: int, layers: int, keep: bool = False)
     return (z, cache) if keep else z
 
 
+def network_full(theta, fat, r, dims, channels: int, layers: int, keep: bool = False):
+    """N r: the network output sum_c W_out[c] psi_L[c] on the full lattice, [V][3]."""
+    p = unpack(theta, channels, layers)
+    e = embed(r, dims, 0)
+    phi = p["W_in"][:, None, None] * e[None]
+    cache = {"e": e, "phi": [], "psi": []}
+    psi = None
+    for l in range(layers):
+        if l >= 1:
+            phi = np.einsum("oi,ivc->ovc", p["W"][l - 1], psi)
+        psi = stencil(fat, p["a"][l], phi, dims)
+        cache["phi"].append(phi)
+        cache["psi"].append(psi)
+    full = np.einsum("c,cvk->vk", p["W_out"], psi)
+    return (full, cache) if keep else full
+
+
+def network_adjoint(theta, fat, u, dims, channels: int, layers: int):
+    """N^dag u for a full-lattice field u [V][3]: an even-site vector [3][V/2]."""
+    p = unpack(theta, channels, layers)
+    g = np.conj(p["W_out"])[:, None, None] * np.asarray(u)[None]
+    for l in reversed(range(layers)):
+        g = stencil_adjoint(fat, p["a"][l], g, dims)
+        if l >= 1:
+            g = np.einsum("oi,ovk->ivk", np.conj(p["W"][l - 1]), g)
+    return extract(np.einsum("c,cvk->vk", np.conj(p["W_in"]), g), dims, 0)
+
+
+def apply(theta, fat, r, dims, channels: int, layers: int, form: str = "direct"):
+    """The preconditioner: R_even N r ("direct") or N^dag N r ("gram")."""
+    if form == "direct":
+        return forward(theta, fat, r, dims, channels, layers)
+    return network_adjoint(theta, fat, network_full(theta, fat, r, dims, channels, layers),
+                           dims, channels, layers)
+
+
+def backprop(theta, fat, x, g_full, dims, channels: int, layers: int):
+    """Wirtinger gradient G with dL = Re sum conj(G) dtheta of L = Re<g_full, N x> for an
+    even-site input x and a full-lattice output gradient g_full."""
+    p = unpack(theta, channels, layers)
+    grad = {"W_in": np.zeros(channels, complex), "W": [np.zeros_like(w) for w in p["W"]],
+            "a": [np.zeros_like(a) for a in p["a"]], "W_out": np.zeros(channels, complex)}
+    _, cache = network_full(theta, fat, x, dims, channels, layers, keep=True)
+    grad["W_out"] += np.einsum("cvk,vk->c", np.conj(cache["psi"][-1]), g_full)
+    gpsi = np.conj(p["W_out"])[:, None, None] * np.asarray(g_full)[None]
+    for l in reversed(range(layers)):
+        phi = cache["phi"][l]
+        hs = _hops(fat, phi, dims)
+        for h in range(9):
+            grad["a"][l][h] += np.einsum("cvk,cvk->c", np.conj(hs[h]), gpsi)
+        gphi = stencil_adjoint(fat, p["a"][l], gpsi, dims)
+        if l >= 1:
+            grad["W"][l - 1] += np.einsum("ovk,ivk->oi", gphi, np.conj(cache["psi"][l - 1]))
+            gpsi = np.einsum("oi,ovk->ivk", np.conj(p["W"][l - 1]), gphi)
+        else:
+            grad["W_in"] += np.einsum("vk,cvk->c", np.conj(cache["e"]), gphi)
+    return pack(grad)
+
+
+def gram_loss_and_grad(theta, fat, rs, ys, dims, channels: int, layers: int, kind="solution",
+                       naik=None, mass=None):
+    """Loss of the Gram form z = N^dag N r and its gradient.  With u = N r and G the gradient
+    of the loss with respect to z, dz = (dN)^dag u + N^dag (dN) r gives
+    dL = Re<u, dN G> + Re<N G, dN r>: two ordinary backward passes, one with input G and
+    output gradient u, one with input r and output gradient N G."""
+    nb = len(rs)
+    tot = 0.0
+    grad = np.zeros(n_params(channels, layers), complex)
+    for r, y in zip(rs, ys):
+        u = network_full(theta, fat, r, dims, channels, layers)
+        z = network_adjoint(theta, fat, u, dims, channels, layers)
+        lj, gz = _pair_loss(z, r, y, kind, fat, naik, dims, mass)
+        tot += lj
+        gz = gz / nb
+        ng = network_full(theta, fat, gz, dims, channels, layers)
+        grad += backprop(theta, fat, gz, u, dims, channels, layers)
+        grad += backprop(theta, fat, r, ng, dims, channels, layers)
+    return tot / nb, grad
+
+
 def _pair_loss(z, r, y, kind, fat, naik, dims, mass):
     """(loss of one pair, Wirtinger gradient with respect to z) before the 1/B factor."""
     if kind == "solution":
@@ -140,10 +225,10 @@ def _pair_loss(z, r, y, kind, fat, naik, dims, mass):
 
 
 def loss(theta, fat, rs, ys, dims, channels: int, layers: int, kind="solution", naik=None,
-         mass=None) -> float:
+         mass=None, form="direct") -> float:
     tot = 0.0
     for r, y in zip(rs, ys):
-        z = forward(theta, fat, r, dims, channels, layers)
+        z = apply(theta, fat, r, dims, channels, layers, form)
         tot += _pair_loss(z, r, y, kind, fat, naik, dims, mass)[0]
     return tot / len(rs)
 

@@ -143,3 +143,44 @@ def test_residual_loss_is_solution_error_in_m2_norm():
     lhs = nn.loss(th, fat, r, y, dims, 2, 2, kind="residual", naik=naik, mass=mass)
     e = (mdense @ (z - y[0]).ravel())
     assert abs(lhs - np.linalg.norm(e) ** 2 / np.linalg.norm(r) ** 2) < 1e-10 * lhs
+
+
+@pytest.mark.parametrize("kind", ["solution", "residual"])
+def test_gram_gradient_matches_finite_differences(kind):
+    c, l = 2, 2
+    fat, naik = synth.gauge_links(DIMS, 48)
+    th = _rand_theta(c, l, 49)
+    rs = synth.sources(DIMS, 2, 50)
+    ys = synth.sources(DIMS, 2, 51)
+    kw = dict(kind=kind, naik=naik, mass=0.3)
+    val, grad = nn.gram_loss_and_grad(th, fat, rs, ys, DIMS, c, l, **kw)
+    assert abs(val - nn.loss(th, fat, rs, ys, DIMS, c, l, form="gram", **kw)) < 1e-12 * val
+    idx = np.random.default_rng(4).choice(th.size, 12, replace=False)
+    h = 1e-6
+    for k in idx:
+        e = np.zeros_like(th)
+        e[k] = h
+        f = lambda t: nn.loss(t, fat, rs, ys, DIMS, c, l, form="gram", **kw)  # noqa: E731
+        d_re = (f(th + e) - f(th - e)) / (2 * h)
+        d_im = (f(th + 1j * e) - f(th - 1j * e)) / (2 * h)
+        scale = max(abs(grad[k]), 1e-3 * np.max(np.abs(grad)))
+        assert abs(grad[k].real - d_re) <= 1e-6 * scale, (k, grad[k], d_re)
+        assert abs(grad[k].imag - d_im) <= 1e-6 * scale, (k, grad[k], d_im)
+
+
+def test_gram_form_is_hermitian_positive_and_adjoint_is_adjoint():
+    c, l = 3, 3
+    fat, _ = synth.gauge_links(DIMS, 52)
+    th = _rand_theta(c, l, 53)
+    a, b = synth.sources(DIMS, 2, 54)
+    vol = int(np.prod(DIMS))
+    g = np.random.default_rng(5)
+    u = g.standard_normal((vol, 3)) + 1j * g.standard_normal((vol, 3))
+    # <u, N a> = <N^dag u, a>
+    lhs = np.vdot(u, nn.network_full(th, fat, a, DIMS, c, l))
+    rhs = np.vdot(nn.network_adjoint(th, fat, u, DIMS, c, l), a)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+    pa = nn.apply(th, fat, a, DIMS, c, l, "gram")
+    pb = nn.apply(th, fat, b, DIMS, c, l, "gram")
+    assert abs(np.vdot(b, pa) - np.conj(np.vdot(a, pb))) < 1e-11 * abs(np.vdot(b, pa))
+    assert np.vdot(a, pa).real > 0 and abs(np.vdot(a, pa).imag) < 1e-11 * abs(np.vdot(a, pa))

@@ -7,8 +7,8 @@ the two half Dslash launches D_oe (even -> odd) and D_eo (odd -> even).
 value = Gflop/s under the 1146 flop per site per rhs convention (Section 1, Table 1 model).
 
 Also reported on the same JSON line:
-  roofline      : compulsory HBM bytes per half-Dslash launch / average launch time (HIP events
-                  on the launch stream), against 8 TB/s;
+  roofline      : compulsory HBM bytes per half-Dslash launch / mean launch duration (HIP events
+                  around each launch of the timed region, on the launch stream), against 8 TB/s;
   dslash_sweep  : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
   cg            : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
                   the mixed-precision solver (FP16 links) and the plain FP64 solver;
@@ -69,7 +69,9 @@ def _events(torch):
 
 
 def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup):
-    """Time `steps` full Dslash applications; returns (ms per step, mean ms per launch)."""
+    """Time `steps` full Dslash applications (D_oe then D_eo) with HIP events on the launch
+    stream: a pair at the ends of the timed region (ms per step, event overhead included) and a
+    pair around every launch inside it (mean kernel duration, the figure a kernel trace gives)."""
     for _ in range(warmup):
         lat.dslash(1, prec, v_e, w_o)
         lat.dslash(0, prec, v_o, w_e)
@@ -112,7 +114,11 @@ def solver_study(args, torch, synth, hisq, pm):
            "link_generation_s": round(t_gen, 1)}
     lib = hisq.library()
 
+    def progress(msg):
+        print(f"[{name}] {msg}", file=sys.stderr, flush=True)
+
     def solve(label, **kw):
+        progress(f"solve {label}")
         torch.cuda.synchronize()
         t = time.perf_counter()
         x, info = lat.cg(mass, b, tol=tol, max_iter=60000, **kw)
@@ -135,20 +141,39 @@ def solver_study(args, torch, synth, hisq, pm):
     r = torch.empty((nsnap * nsrc, 3, lat.vh), dtype=torch.complex128, device=dev)
     y = torch.empty_like(r)
     npairs = ctypes.c_int()
+    progress("harvest training pairs")
     torch.cuda.synchronize()
     t = time.perf_counter()
     hisq._check(lat.ctx, lib.hisq_nn_harvest(lat.ctx, mass, nsrc, hisq._ptr(bs), 1e-8, nsnap,
                                              60, hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
     out["harvest"] = {"pairs": npairs.value, "seconds": round(time.perf_counter() - t, 2)}
+    # Gram form N^dag N (Hermitian positive semi-definite) trained on the residual-norm loss
     hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, 4, 8, seed))
+    hisq._check(lat.ctx, lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM))
+    hisq._check(lat.ctx, lib.hisq_nn_set_loss(lat.ctx, hisq.HISQ_NN_LOSS_RESIDUAL, mass))
     hist = (ctypes.c_double * args.epochs)()
+    batch, lr = 16, 1e-2
+    progress("train the network")
     t = time.perf_counter()
     hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
-                                           args.epochs, 8, 3e-3, seed, hist))
-    out["training"] = {"epochs": args.epochs, "batch": 8, "lr": 3e-3, "bf16": True,
-                       "seconds": round(time.perf_counter() - t, 2),
+                                           args.epochs, batch, lr, seed, hist))
+    out["training"] = {"form": "gram", "loss": "residual", "epochs": args.epochs, "batch": batch,
+                       "lr": lr, "bf16": True, "seconds": round(time.perf_counter() - t, 2),
                        "loss_first": round(hist[0], 5), "loss_last": round(hist[args.epochs - 1], 5)}
     del r, y
+    # one preconditioner application on the n-rhs bundle (FP32 vectors), as inside the FCG
+    rv = b.to(torch.complex64)
+    zv = torch.empty_like(rv)
+    for _ in range(2):
+        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, n, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
+    e0, e1 = _events(torch)
+    e0.record()
+    for _ in range(5):
+        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, n, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
+    e1.record()
+    torch.cuda.synchronize()
+    out["network_apply_ms"] = round(e0.elapsed_time(e1) / 5, 3)
+    del rv, zv
     solve("fcg_learned_f16links", kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F16)
     out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out["mixed_f16links"]["seconds"], 3)
     out["speedup_fcg_vs_mixed"] = round(out["mixed_f16links"]["seconds"] / out["fcg_learned_f16links"]["seconds"], 3)
@@ -169,7 +194,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
                     help="c1: Dslash throughput at 32^3x8 (default, the timed steps); c3/c4: the "
                          "solver comparison at 48^3x12 / 64^3x16 (plain FP64, mixed, learned FCG)")
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), then --steps FP32 Dslash steps")
@@ -207,12 +232,11 @@ def main():
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
-        for _ in range(args.steps):
-            lat.dslash(1, hisq.HISQ_F32, v_e, w_o)
-            lat.dslash(0, hisq.HISQ_F32, v_o, w_e)
-        torch.cuda.synchronize()
+        _, ms_launch = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
+                                          args.steps, 0)
         print(f"profile run done: {args.steps} steps, {n} rhs, lattice {dims}, launch "
-              f"{hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)}, source {kernel_source_hash()}")
+              f"{hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)}, source {kernel_source_hash()}, "
+              f"event-timed {ms_launch * 1e3:.1f} us per launch")
         lat.close()
         return
 

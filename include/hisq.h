@@ -132,7 +132,8 @@ typedef struct {
                          /*    LDS for 64 sites' links: not FP64)                                */
   int xcd_map;           /* LDS form only: 0 = each XCD takes a contiguous range of sites; 1 =    */
                          /*    each XCD takes Lz/8 z slices for all t (needs (Lx/2)*Ly % 64 == 0 */
-                         /*    and Lz % 8 == 0)                                                  */
+                         /*    and Lz % 8 == 0); 2 = each XCD takes 1/8 of the 64-site blocks of */
+                         /*    every (z, t) plane, z-major (needs (Lx/2)*Ly % 512 == 0)          */
 } hisq_launch;
 
 /* Force the configuration for (prec, n), both forms (the fused-M form clamps rhs_per_thread to
@@ -212,6 +213,15 @@ int hisq_nn_get_params(hisq_ctx *ctx, double *out, int n_reals);
 int hisq_nn_set_params(hisq_ctx *ctx, const double *in, int n_reals);
 /* Activation storage: 1 = BF16 (default), 0 = FP32. */
 int hisq_nn_set_precision(hisq_ctx *ctx, int bf16_storage);
+/* Form of the preconditioner built from the network N (N r = sum_c W_out[c] psi_L[c] on the
+ * full lattice):
+ *   HISQ_NN_FORM_DIRECT (default): P r = N r restricted to the even sites;
+ *   HISQ_NN_FORM_GRAM:             P r = N^dag N r, Hermitian positive semi-definite for any
+ *                                  weights (the property CG-type solvers assume of a
+ *                                  preconditioner); each application costs two network passes.
+ * The form applies to hisq_nn_apply, the loss, training and HISQ_FCG_NN, and is saved. */
+enum { HISQ_NN_FORM_DIRECT = 0, HISQ_NN_FORM_GRAM = 1 };
+int hisq_nn_set_form(hisq_ctx *ctx, int form);
 
 /* Training loss for pairs (r_j, y_j = M^-1 r_j) over a minibatch of B pairs:
  *   HISQ_NN_LOSS_SOLUTION (default): (1/B) sum_j ||P r_j - y_j||^2 / ||y_j||^2
@@ -240,7 +250,9 @@ int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const void *y, int 
 int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b, double tol, int n_snap,
                     int snap_every, void *r_out, void *y_out, int *n_pairs);
 
-/* Save / load the parameters (binary: 4 int32 header, then the reals as float64). */
+/* Save / load the network (binary: int32 header {magic 0x51534948, version 2, layers, channels,
+ * form}, then the parameters as float64 reals; version 1 files, without the form, load as the
+ * direct form). */
 int hisq_nn_save(hisq_ctx *ctx, const char *path);
 int hisq_nn_load(hisq_ctx *ctx, const char *path);
 

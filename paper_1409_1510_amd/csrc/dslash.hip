@@ -27,7 +27,8 @@ DslashFn lookup(int prec, int recon, bool epi, const hisq_launch &c) {
 size_t lds_bytes(int prec, int recon, const hisq_launch &c) {
   if (!c.lds_links) return 0;
   const size_t elem = prec == HISQ_F64 ? 16 : (prec == HISQ_F32 ? 8 : 4);
-  return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem;
+  const size_t row2 = (prec != HISQ_F64 && recon == 14) ? size_t(24) * 64 * (prec == HISQ_F64 ? 16 : 8) : 0;
+  return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem + row2;
 }
 
 bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size_t lds_max = 0) {
@@ -37,7 +38,7 @@ bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size
   if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
   if (c.lds_links < 0 || c.lds_links > 3) return false;
-  if (c.xcd_map != 0 && (c.xcd_map != 1 || !c.lds_links)) return false;
+  if (c.xcd_map < 0 || c.xcd_map > 2 || (c.xcd_map != 0 && !c.lds_links)) return false;
   return lookup(prec, 18, epi, c) != nullptr && lookup(prec, 14, epi, c) != nullptr;
 }
 
@@ -56,14 +57,26 @@ hisq_launch heuristic(int prec, int n, bool epi) {
 }
 
 struct Geo {
-  int ntiles, ngroups, nsblk, grid, zmap_bps, zmap_zr;
+  int ntiles, ngroups, nsblk, grid, xmap, zmap_bps, zmap_zr;
 };
 
-// the z-slab XCD map needs whole 64-site blocks per (z, t) slab and Lz divisible by 8
-bool zmap_possible(const Geometry &g) { return (g.lxh * g.ly) % 64 == 0 && g.lz % 8 == 0; }
+// XCD maps: both need whole 64-site blocks per (z, t) plane; the z-slab map (1) needs Lz
+// divisible by 8, the y-slab map (2) a multiple of 8 blocks per plane
+bool map_possible(const Geometry &g, int xm) {
+  if (xm == 0) return true;
+  if ((g.lxh * g.ly) % 64 != 0) return false;
+  if (xm == 1) return g.lz % 8 == 0;
+  if (xm == 2) return (g.lxh * g.ly / 64) % 8 == 0;
+  return false;
+}
+const char *map_requirement(int xm) {
+  return xm == 1 ? "the z-slab XCD map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0"
+                 : "the y-slab XCD map needs (Lx/2)*Ly % 512 == 0";
+}
 
 Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
   Geo o;
+  o.xmap = 0;
   o.zmap_bps = 0;
   o.zmap_zr = 0;
   o.ntiles = (n + c.rhs_per_thread - 1) / c.rhs_per_thread;
@@ -72,10 +85,11 @@ Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
   o.nsblk = (g.vh + c.sites_per_block - 1) / c.sites_per_block;
   const int nb = o.nsblk * o.ngroups;
   o.grid = (nb + 7) / 8 * 8;
-  if (c.lds_links && c.xcd_map == 1 && zmap_possible(g)) {
+  if (c.lds_links && c.xcd_map && map_possible(g, c.xcd_map)) {
+    o.xmap = c.xcd_map;
     o.zmap_bps = g.lxh * g.ly / 64;
     o.zmap_zr = g.lz / 8;
-    o.grid = 8 * g.lt * o.zmap_zr * o.zmap_bps;  // == nsblk
+    o.grid = o.nsblk;  // 8 * Lt * (Lz/8) * bps (z slabs) or 8 * Lz * Lt * (bps/8) (y slabs)
   }
   return o;
 }
@@ -89,10 +103,9 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
     return set_err(ctx, HISQ_ERR_ARG, "Dslash launch configuration needs %zu bytes of LDS (%zu available)",
                    lds_bytes(prec, l.recon, c), ctx->lds_max);
   const Geo geo = geometry(ctx->g, n, c);
-  if (c.xcd_map == 1 && !geo.zmap_bps)
-    return set_err(ctx, HISQ_ERR_ARG, "the z-slab XCD map needs (Lx/2)*Ly %% 64 == 0 and Lz %% 8 == 0");
+  if (c.xcd_map && geo.xmap != c.xcd_map) return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
-         mass2, pvec, partial, active, geo.zmap_bps, geo.zmap_zr};
+         mass2, pvec, partial, active, geo.xmap, geo.zmap_bps, geo.zmap_zr};
   fn(a, dim3(geo.grid), ctx->stream);
   LAUNCHCHK(ctx, "k_dslash");
   return HISQ_OK;
@@ -118,6 +131,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   RETCHK(ws_get(ctx, WS_TUNE1, bytes, &b));
   RETCHK(ws_get(ctx, WS_TUNE2, size_t(n) * dslash_partials(g) * sizeof(double), &pp));
   HIPCHK(ctx, hipMemsetAsync(a, 0, bytes, ctx->stream));
+  HIPCHK(ctx, hipMemsetAsync(b, 0, bytes, ctx->stream));
   hipEvent_t e0, e1;
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
@@ -126,16 +140,21 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   const int rts[] = {1, 2, 4, 8, 16};
   int rc = HISQ_OK;
   std::vector<std::pair<float, hisq_launch>> timed;
+  // launches alternate between the two output parities (a -> b, b -> a), as in D = D_oe + D_eo
+  // and in the solvers: repeating one parity would let the 256 MB last-level cache keep that
+  // parity's links and time a cache-resident case
   auto time_cfg = [&](const hisq_launch &c, int reps, float *ms_out) -> int {
-    for (int k = 0; k <= reps; ++k) {
+    for (int k = 0; k <= 2 * reps; ++k) {
       if (k == 1) (void)hipEventRecord(e0, ctx->stream);
-      RETCHK(run(ctx, epi ? 0 : 1, prec, n, a, b, epi, 0.01, a, static_cast<double *>(pp), nullptr, c));
+      const bool odd = k & 1;
+      RETCHK(run(ctx, odd ? 0 : 1, prec, n, odd ? b : a, odd ? a : b, epi, 0.01, odd ? b : a,
+                 static_cast<double *>(pp), nullptr, c));
     }
     (void)hipEventRecord(e1, ctx->stream);
     (void)hipEventSynchronize(e1);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    *ms_out = ms / reps;
+    *ms_out = ms / (2 * reps);
     return HISQ_OK;
   };
   for (int rt : rts) {
@@ -143,10 +162,10 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
     for (int spb : {256, 64})
       for (int nt : {0, 1})
         for (int lds : {0, 1, 2, 3})
-          for (int xm : {0, 1}) {
+          for (int xm : {0, 1, 2}) {
             hisq_launch c{rt, spb, nt, lds, xm};
             if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
-            if (xm && !zmap_possible(g)) continue;
+            if (!map_possible(g, xm)) continue;
             float ms;
             rc = time_cfg(c, 3, &ms);
             if (rc != HISQ_OK) break;
@@ -220,8 +239,8 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
     }
     hisq_launch c = *cfg;
     const int recon = ctx->links[prec].base ? ctx->links[prec].recon : 18;
-    if (c.xcd_map == 1 && !zmap_possible(ctx->g))
-      return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: the z-slab XCD map needs (Lx/2)*Ly %% 64 == 0 and Lz %% 8 == 0");
+    if (c.xcd_map >= 1 && c.xcd_map <= 2 && !map_possible(ctx->g, c.xcd_map))
+      return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
     if (!config_valid(prec, epi, c, recon, ctx->lds_max)) {
       if (epi) {  // the fused-M form caps the register tile: use the largest valid one
         while (c.rhs_per_thread > 1 && !config_valid(prec, true, c, recon, ctx->lds_max))
@@ -306,7 +325,7 @@ extern "C" int hisq_load_tuning(hisq_ctx *ctx, const char *path, int *n_loaded) 
     if (prec < 0 || prec > 2 || n < 1 || n > HISQ_MAX_RHS || (e != 0 && e != 1)) continue;
     if (!ctx->links[prec].base || ctx->links[prec].recon != recon) continue;
     if (!config_valid(prec, e != 0, c, recon, ctx->lds_max)) continue;
-    if (c.xcd_map && !zmap_possible(g)) continue;
+    if (!map_possible(g, c.xcd_map)) continue;
     TuneEntry &t = ctx->tune[prec][n][e];
     t.cfg = c;
     t.state = TuneEntry::TUNED;

@@ -68,6 +68,23 @@ template <typename Real> struct Lnk {
   Real re[3][3], im[3][3];
 };
 
+// Row 2 of a 14-real Naik link from rows 0 and 1 and the stored scale z: z * conj(row0 x row1).
+template <typename Real>
+__device__ inline void naik_row2(Lnk<Real> &L, Real zr, Real zi) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+    // cross_b = r0[b1] r1[b2] - r0[b2] r1[b1]
+    Real cr = (L.re[0][b1] * L.re[1][b2] - L.im[0][b1] * L.im[1][b2]) -
+              (L.re[0][b2] * L.re[1][b1] - L.im[0][b2] * L.im[1][b1]);
+    Real ci = (L.re[0][b1] * L.im[1][b2] + L.im[0][b1] * L.re[1][b2]) -
+              (L.re[0][b2] * L.im[1][b1] + L.im[0][b2] * L.re[1][b1]);
+    // row2_b = z * conj(cross_b)
+    L.re[2][b] = zr * cr + zi * ci;
+    L.im[2][b] = zi * cr - zr * ci;
+  }
+}
+
 // Load the link of a hop at site s; a 14-real Naik link gets row 2 = z * conj(row0 x row1).
 template <typename Real, typename LT, bool R14, bool NT>
 __device__ inline void load_link(const LT *__restrict__ links, int plane, unsigned vh, unsigned s,
@@ -81,18 +98,7 @@ __device__ inline void load_link(const LT *__restrict__ links, int plane, unsign
   if constexpr (R14) {
     Real zr, zi;
     ld_link<NT>(p + 6 * vh, zr, zi);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
-      // cross_b = r0[b1] r1[b2] - r0[b2] r1[b1]
-      Real cr = (L.re[0][b1] * L.re[1][b2] - L.im[0][b1] * L.im[1][b2]) -
-                (L.re[0][b2] * L.re[1][b1] - L.im[0][b2] * L.im[1][b1]);
-      Real ci = (L.re[0][b1] * L.im[1][b2] + L.im[0][b1] * L.re[1][b2]) -
-                (L.re[0][b2] * L.im[1][b1] + L.im[0][b2] * L.re[1][b1]);
-      // row2_b = z * conj(cross_b)
-      L.re[2][b] = zr * cr + zi * ci;
-      L.im[2][b] = zi * cr - zr * ci;
-    }
+    naik_row2(L, zr, zi);
   }
 }
 
@@ -137,8 +143,9 @@ struct Args {
   const void *pvec;       // epilogue: q = mass2 * pvec - D in
   double *partial;        // epilogue: Re<pvec, q> per rhs per 64-site wave, [n][ceil(V/2 / 64)]
   const int *active;      // per-rhs mask or null
-  int zmap_bps;           // LDS form, z-slab XCD map: 64-site blocks per (z, t) slab (0 = off)
-  int zmap_zr;            //   z slices owned by each XCD (Lz / 8)
+  int xmap;               // LDS form, XCD map: 0 contiguous ranges, 1 z slabs, 2 y slabs
+  int zmap_bps;           //   64-site blocks per (z, t) plane
+  int zmap_zr;            //   z-slab map: z slices owned by each XCD (Lz / 8)
 };
 
 // SPB: sites per 256-thread workgroup (256: one tile per workgroup; 64: 4 tiles, one per wave).
@@ -268,6 +275,29 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
   }
 }
 
+// Naik link k (0..7: hops 8 + k) of lane `lane` from the staged LDS copy: rows 0 and 1 from the
+// stored planes and, for 14-real links, row 2 from the planes rebuilt once per site.
+template <typename Real, typename LT, bool R14>
+__device__ inline void load_naik_lds(const LT *__restrict__ sl, const typename CT<Real>::T *__restrict__ row2,
+                                     int k, int lane, Lnk<Real> &L) {
+  const int recon = R14 ? 14 : 18;
+  if constexpr (!R14) {
+    load_link<Real, LT, false, false>(sl, link_plane(8 + k, recon), 64u, unsigned(lane), L);
+  } else {
+    const LT *p = sl + link_plane(8 + k, recon) * 64 + lane;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) ld_link<false>(p + (a * 3 + b) * 64, L.re[a][b], L.im[a][b]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const typename CT<Real>::T v = row2[(k * 3 + b) * 64 + lane];
+      L.re[2][b] = v.x;
+      L.im[2][b] = v.y;
+    }
+  }
+}
+
 // LDS-staged form: a workgroup of 64 sites x WPB waves first copies the links of its 64 sites
 // (all 16 hops) into LDS, then the waves loop over the rhs tiles (wave w takes tiles w, w+WPB,
 // ...), reading the links from LDS for every tile.  Only WPB*RT rhs of a site block are in
@@ -285,7 +315,18 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
   LT *sl = reinterpret_cast<LT *>(smem_raw);
   const Geometry &g = a.g;
   int sblk;
-  if (a.zmap_bps) {
+  if (a.xmap == 2) {
+    // XCD k owns the blocks [k, k+1) * bps/8 of every (z, t) plane (with Lx = 32: four y rows)
+    // and walks the planes z-major.  The sites in flight on an XCD then span a few z slices of a
+    // thin slab whose t extent is the whole lattice, so the t and z neighbours they gather (the
+    // Naik hops reach 3 slices away) are mostly still in that XCD's L2.
+    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int bpx = a.zmap_bps >> 3;
+    const int zt = j / bpx;  // z * Lt + t
+    const int z = zt / g.lt, t = zt - z * g.lt;
+    if (z >= g.lz) return;  // uniform for the whole workgroup
+    sblk = (t * g.lz + z) * a.zmap_bps + k * bpx + (j - zt * bpx);
+  } else if (a.xmap == 1) {
     // XCD k owns the z slices [k Lz/8, (k+1) Lz/8) for every t: the z and t neighbours of its
     // sites stay mostly in its own L2 (with contiguous chunks, Lt = 8 would give each XCD a single
     // t slice and send every t hop to another XCD's data)
@@ -325,6 +366,24 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
       }
     }
   __syncthreads();
+  // 14-real Naik links: rebuild row 2 once per site (not once per rhs tile) into LDS planes of
+  // the arithmetic type after the stored planes, with the same arithmetic as load_link
+  C *row2 = reinterpret_cast<C *>(sl + PL * 64);
+  if constexpr (R14) {
+    for (int item = threadIdx.x; item < 8 * 64; item += 64 * WPB) {
+      const int k = item >> 6, ln = item & 63;
+      Lnk<Real> Lk;
+      load_link<Real, LT, true, false>(sl, link_plane(8 + k, recon), 64u, ln, Lk);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        C v;
+        v.x = Lk.re[2][b];
+        v.y = Lk.im[2][b];
+        row2[(k * 3 + b) * 64 + ln] = v;
+      }
+    }
+    __syncthreads();
+  }
 
   int x = 0, y = 0, z = 0, t = 0;
   if (valid) {
@@ -379,9 +438,9 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
         apply_hop<Real, RT, false>(Lk, in, vh, f1, act, acc_re, acc_im);
         load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
         apply_hop<Real, RT, true>(Lk, in, vh, b1, act, acc_re, acc_im);
-        load_link<Real, LT, R14, false>(sl, link_plane(8 + mu, recon), 64u, lane, Lk);
+        load_naik_lds<Real, LT, R14>(sl, row2, mu, lane, Lk);
         apply_hop<Real, RT, false>(Lk, in, vh, f3, act, acc_re, acc_im);
-        load_link<Real, LT, R14, false>(sl, link_plane(12 + mu, recon), 64u, lane, Lk);
+        load_naik_lds<Real, LT, R14>(sl, row2, 4 + mu, lane, Lk);
         apply_hop<Real, RT, true>(Lk, in, vh, b3, act, acc_re, acc_im);
       }
     }
@@ -439,7 +498,9 @@ void launch_t(const Args &a, dim3 grid, hipStream_t st) {
 
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
 void launch_lds(const Args &a, dim3 grid, hipStream_t st) {
-  constexpr size_t lds = size_t(R14 ? 128 : 144) * 64 * sizeof(LT);
+  // 14-real Naik: the stored planes plus 8 x 3 rebuilt row-2 entries in the arithmetic type
+  constexpr size_t lds = size_t(R14 ? 128 : 144) * 64 * sizeof(LT) +
+                         (R14 ? size_t(24) * 64 * sizeof(typename CT<Real>::T) : 0);
   k_dslash_lds<Real, LT, RT, R14, EPI, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
 }
 

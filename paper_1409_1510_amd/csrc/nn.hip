@@ -3,7 +3,8 @@
 // per-channel gauge-covariant one-hop stencil over the fat links X of Eq. 3:
 //
 //   phi_1 = W_in (x) E(r);  psi_l = S(a_l, phi_l);  phi_l = W_l psi_{l-1} (l >= 2);
-//   z = R_even(sum_c W_out[c] psi_L[c]);
+//   N r = sum_c W_out[c] psi_L[c] (full lattice);
+//   direct form: z = R_even N r;  Gram form: z = N^dag N r (Hermitian positive semi-definite).
 //   S(a, phi)_c(x) = a[0,c] phi_c(x) + sum_mu (a[1+mu,c] X(x,mu) phi_c(x+mu)
 //                                            + a[5+mu,c] X(x-mu,mu)^dag phi_c(x-mu)).
 //
@@ -158,10 +159,10 @@ template <typename AT, typename LT, bool ADJ>
 __global__ void __launch_bounds__(kThreads)
 k_nn_stencil(NNArgs A, const AT *__restrict__ in, AT *__restrict__ out, const float2 *__restrict__ a) {
   const Geometry &g = A.g;
-  const unsigned X = blockIdx.x * kThreads + threadIdx.x;
-  const unsigned V = 2u * g.vh;
+  const unsigned X = (blockIdx.x / A.batch) * kThreads + threadIdx.x;  // samples fastest: the
+  const unsigned V = 2u * g.vh;                                        // links are shared in L2
   if (X >= V) return;
-  const size_t boff = size_t(blockIdx.y) * A.sample_stride;
+  const size_t boff = size_t(blockIdx.x % A.batch) * A.sample_stride;
   const AT *__restrict__ ib = in + boff;
   AT *__restrict__ ob = out + boff;
   const Site q = decode(g, X);
@@ -214,6 +215,173 @@ k_nn_stencil(NNArgs A, const AT *__restrict__ in, AT *__restrict__ out, const fl
   }
 #pragma unroll
   for (int col = 0; col < 3; ++col) Act<AT>::store(ob + (size_t(col) * V + X) * NR, acc[col]);
+}
+
+// ---- fused inference layer -----------------------------------------------------------------
+// One pass of the network for inference (no activations kept for a backward pass): the stencil
+// S(a) (or S^dag(a)) of one layer followed in registers by what comes next, so that each layer
+// reads and writes the activations once:
+//   input  : an activation buffer, or (IN_VEC) a vector v [b][3][vin_sites] (vin_sites = V/2:
+//            zero on odd sites) lifted to the channels with coefficients win (conjugated if
+//            in_conj): phi_c = win[c] v, so every hop applies its link once for all channels;
+//   output : (OUT_VEC) the readout z = sum_c wout[c] psi_c (conjugated if out_conj) on the first
+//            out_sites sites ([b][3][out_sites]), or the activation mix W psi (W^dag if
+//            mix_conjt) written to an activation buffer on the full lattice.
+// The arithmetic is FP32; stored activations are AT.
+struct FusedArgs {
+  NNArgs A;
+  const void *in;          // activation buffer or float2 vector
+  void *out;               // activation buffer or float2 vector
+  const float2 *a;         // stencil coefficients a[9][C]
+  const float2 *w;         // post-mix matrix W[C][C] ([out][in])
+  const float2 *win, *wout;
+  unsigned vin_sites, out_sites;
+  int in_conj, out_conj, mix_conjt;
+};
+
+// Grid: one workgroup per (256-site block, sample), samples fastest, so the workgroups that
+// run together share their sites' links through L2.
+template <typename AT, typename LT, bool ADJ, bool IN_VEC, bool OUT_VEC>
+__global__ void __launch_bounds__(kThreads) k_nn_layer(FusedArgs F) {
+  const Geometry &g = F.A.g;
+  const unsigned V = 2u * g.vh;
+  const int b = blockIdx.x % F.A.batch;
+  const unsigned X = (blockIdx.x / F.A.batch) * kThreads + threadIdx.x;
+  if (X >= F.out_sites) return;
+  const Site q = decode(g, X);
+  float acc[3][NR];
+  float2 cin[NC];  // IN_VEC: a[h][c] * win[c] is formed per hop
+  if constexpr (IN_VEC) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      cin[c] = F.win[c];
+      if (F.in_conj) cin[c].y = -cin[c].y;
+    }
+  }
+  const AT *ib = nullptr;
+  const float2 *vb = nullptr;
+  if constexpr (IN_VEC) vb = static_cast<const float2 *>(F.in) + size_t(b) * 3 * F.vin_sites;
+  else ib = static_cast<const AT *>(F.in) + size_t(b) * F.A.sample_stride;
+  // self term
+  if constexpr (IN_VEC) {
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+      const float2 v = X < F.vin_sites ? vb[size_t(col) * F.vin_sites + X] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float2 w = cmulf(coef<ADJ>(F.a, 0, c), cin[c]);
+        acc[col][2 * c] = w.x * v.x - w.y * v.y;
+        acc[col][2 * c + 1] = w.x * v.y + w.y * v.x;
+      }
+    }
+  } else {
+    float v[NR];
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+      Act<AT>::load(ib + (size_t(col) * V + X) * NR, v);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float2 w = coef<ADJ>(F.a, 0, c);
+        acc[col][2 * c] = w.x * v[2 * c] - w.y * v[2 * c + 1];
+        acc[col][2 * c + 1] = w.x * v[2 * c + 1] + w.y * v[2 * c];
+      }
+    }
+  }
+  // an even-site input vector has nothing on the neighbours of an even site
+  const bool hops = !IN_VEC || F.vin_sites > unsigned(g.vh) || q.p == 1;
+  const LT *__restrict__ lk = static_cast<const LT *>(F.A.links[q.p]);
+  if (hops) {
+#pragma unroll 1
+    for (int h = 1; h < 9; ++h) {
+      const int mu = (h - 1) & 3;
+      const bool fwd = h < 5;
+      const unsigned nb = nbr1(g, q, mu, fwd ? 1 : -1);
+      const int plane = link_plane(fwd ? mu : 4 + mu, 18);
+      float lr[3][3], li[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) ld_link(lk + size_t(plane + 3 * i + j) * g.vh + q.s, lr[i][j], li[i][j]);
+      if constexpr (IN_VEC) {
+        if (nb >= F.vin_sites) continue;
+        float2 v[3];
+#pragma unroll
+        for (int col = 0; col < 3; ++col) v[col] = vb[size_t(col) * F.vin_sites + nb];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          float tr = 0.f, ti = 0.f;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            tr = fmaf(lr[i][j], v[j].x, tr);
+            tr = fmaf(-li[i][j], v[j].y, tr);
+            ti = fmaf(lr[i][j], v[j].y, ti);
+            ti = fmaf(li[i][j], v[j].x, ti);
+          }
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const float2 w = cmulf(coef<ADJ>(F.a, h, c), cin[c]);
+            acc[i][2 * c] = fmaf(w.x, tr, fmaf(-w.y, ti, acc[i][2 * c]));
+            acc[i][2 * c + 1] = fmaf(w.x, ti, fmaf(w.y, tr, acc[i][2 * c + 1]));
+          }
+        }
+      } else {
+        float v[3][NR];
+#pragma unroll
+        for (int col = 0; col < 3; ++col) Act<AT>::load(ib + (size_t(col) * V + nb) * NR, v[col]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const float2 w = coef<ADJ>(F.a, h, c);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            float tr = 0.f, ti = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              tr = fmaf(lr[i][j], v[j][2 * c], tr);
+              tr = fmaf(-li[i][j], v[j][2 * c + 1], tr);
+              ti = fmaf(lr[i][j], v[j][2 * c + 1], ti);
+              ti = fmaf(li[i][j], v[j][2 * c], ti);
+            }
+            acc[i][2 * c] = fmaf(w.x, tr, fmaf(-w.y, ti, acc[i][2 * c]));
+            acc[i][2 * c + 1] = fmaf(w.x, ti, fmaf(w.y, tr, acc[i][2 * c + 1]));
+          }
+        }
+      }
+    }
+  }
+  if constexpr (OUT_VEC) {
+    float2 *zb = static_cast<float2 *>(F.out) + size_t(b) * 3 * F.out_sites;
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const float wr = F.wout[c].x, wi = F.out_conj ? -F.wout[c].y : F.wout[c].y;
+        re = fmaf(wr, acc[col][2 * c], fmaf(-wi, acc[col][2 * c + 1], re));
+        im = fmaf(wr, acc[col][2 * c + 1], fmaf(wi, acc[col][2 * c], im));
+      }
+      zb[size_t(col) * F.out_sites + X] = make_float2(re, im);
+    }
+  } else {
+    AT *ob = static_cast<AT *>(F.out) + size_t(b) * F.A.sample_stride;
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+      float o[NR];
+#pragma unroll
+      for (int p = 0; p < NC; ++p) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          float2 m = F.mix_conjt ? F.w[c * NC + p] : F.w[p * NC + c];
+          if (F.mix_conjt) m.y = -m.y;
+          re = fmaf(m.x, acc[col][2 * c], fmaf(-m.y, acc[col][2 * c + 1], re));
+          im = fmaf(m.x, acc[col][2 * c + 1], fmaf(m.y, acc[col][2 * c], im));
+        }
+        o[2 * p] = re;
+        o[2 * p + 1] = im;
+      }
+      Act<AT>::store(ob + (size_t(col) * V + X) * NR, o);
+    }
+  }
 }
 
 // Real 16 x 16 form of the complex channel mixing M (out = M in), interleaved (re, im) per
@@ -291,10 +459,12 @@ k_nn_mix_mfma(const bf16 *__restrict__ in, bf16 *__restrict__ out, size_t ncols,
   }
 }
 
-// out[b][col][X][c] = w[c] * (X even ? v[b][col][X] : 0); w = coefficients (conj if CONJW)
+// out[b][col][X][c] = w[c] * (X < vs ? v[b][col][X] : 0); w = coefficients (conj if CONJW).
+// vs = V/2 for an even-site vector (zero on odd sites), V for a full-lattice vector.
 template <typename AT, bool CONJW>
 __global__ void __launch_bounds__(kThreads)
-k_nn_embed(const float2 *__restrict__ v, AT *__restrict__ out, NNArgs A, const float2 *__restrict__ w) {
+k_nn_embed(const float2 *__restrict__ v, unsigned vs, AT *__restrict__ out, NNArgs A,
+           const float2 *__restrict__ w) {
   const Geometry &g = A.g;
   const unsigned V = 2u * g.vh;
   const unsigned X = blockIdx.x * kThreads + threadIdx.x;
@@ -304,7 +474,7 @@ k_nn_embed(const float2 *__restrict__ v, AT *__restrict__ out, NNArgs A, const f
 #pragma unroll
   for (int col = 0; col < 3; ++col) {
     float2 r = make_float2(0.f, 0.f);
-    if (X < unsigned(g.vh)) r = v[(size_t(b) * 3 + col) * g.vh + X];
+    if (X < vs) r = v[(size_t(b) * 3 + col) * vs + X];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       float2 wc = w[c];
@@ -317,14 +487,16 @@ k_nn_embed(const float2 *__restrict__ v, AT *__restrict__ out, NNArgs A, const f
   }
 }
 
-// z[b][col][s] = sum_c w[c] act[b][col][s][c] on even sites
-template <typename AT>
+// z[b][col][s] = sum_c w[c] act[b][col][s][c] (conj(w[c]) if CONJW) for s < vs (V/2: even
+// sites; V: the full lattice)
+template <typename AT, bool CONJW>
 __global__ void __launch_bounds__(kThreads)
-k_nn_readout(const AT *__restrict__ act, float2 *__restrict__ z, NNArgs A, const float2 *__restrict__ w) {
+k_nn_readout(const AT *__restrict__ act, float2 *__restrict__ z, unsigned vs, NNArgs A,
+             const float2 *__restrict__ w) {
   const Geometry &g = A.g;
   const unsigned V = 2u * g.vh;
   const unsigned s = blockIdx.x * kThreads + threadIdx.x;
-  if (s >= unsigned(g.vh)) return;
+  if (s >= vs) return;
   const int b = blockIdx.y;
 #pragma unroll
   for (int col = 0; col < 3; ++col) {
@@ -333,10 +505,11 @@ k_nn_readout(const AT *__restrict__ act, float2 *__restrict__ z, NNArgs A, const
     float re = 0.f, im = 0.f;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      re = fmaf(w[c].x, v[2 * c], fmaf(-w[c].y, v[2 * c + 1], re));
-      im = fmaf(w[c].x, v[2 * c + 1], fmaf(w[c].y, v[2 * c], im));
+      const float wr = w[c].x, wi = CONJW ? -w[c].y : w[c].y;
+      re = fmaf(wr, v[2 * c], fmaf(-wi, v[2 * c + 1], re));
+      im = fmaf(wr, v[2 * c + 1], fmaf(wi, v[2 * c], im));
     }
-    z[(size_t(b) * 3 + col) * g.vh + s] = make_float2(re, im);
+    z[(size_t(b) * 3 + col) * vs + s] = make_float2(re, im);
   }
 }
 
@@ -368,11 +541,11 @@ k_nn_loss(const float2 *__restrict__ z, const float2 *__restrict__ y, const doub
   if (threadIdx.x == 0) partial[size_t(b) * gridDim.x + blockIdx.x] = acc;
 }
 
-// per-block partials of G[c] = sum (CONJ_ACT ? conj(act_c) v : conj(v) act_c) over even sites,
-// colours, samples; partial layout [blk][c][re, im]
+// per-block partials of G[c] = sum (CONJ_ACT ? conj(act_c) v : conj(v) act_c) over the first vs
+// sites (V/2: even sites, V: full lattice), colours, samples; partial layout [blk][c][re, im]
 template <typename AT, bool CONJ_ACT>
 __global__ void __launch_bounds__(kThreads)
-k_nn_chan_dot(const AT *__restrict__ act, const float2 *__restrict__ v, NNArgs A,
+k_nn_chan_dot(const AT *__restrict__ act, const float2 *__restrict__ v, unsigned vs, NNArgs A,
               double *__restrict__ partial) {
   __shared__ double red[4];
   const Geometry &g = A.g;
@@ -380,11 +553,11 @@ k_nn_chan_dot(const AT *__restrict__ act, const float2 *__restrict__ v, NNArgs A
   double acc[2 * NC];
 #pragma unroll
   for (int k = 0; k < 2 * NC; ++k) acc[k] = 0.0;
-  const size_t total = size_t(A.batch) * 3 * g.vh;
+  const size_t total = size_t(A.batch) * 3 * vs;
   for (size_t j = size_t(blockIdx.x) * kThreads + threadIdx.x; j < total; j += size_t(gridDim.x) * kThreads) {
-    const size_t b = j / (3 * size_t(g.vh));
-    const size_t rem = j - b * 3 * size_t(g.vh);
-    const unsigned col = rem / g.vh, s = rem % g.vh;
+    const size_t b = j / (3 * size_t(vs));
+    const size_t rem = j - b * 3 * size_t(vs);
+    const unsigned col = rem / vs, s = rem % vs;
     float a[NR];
     Act<AT>::load(act + b * A.sample_stride + (size_t(col) * V + s) * NR, a);
     const float2 w = v[j];
@@ -516,15 +689,15 @@ k_nn_mix_wgrad(const AT *__restrict__ gphi, const AT *__restrict__ psi, size_t n
   partial[size_t(blockIdx.x) * NR * NR + threadIdx.x] = acc;
 }
 
-// sum of partial rows: out[k] = sum_b partial[b * width + k]
+// sum of partial rows: out[k] = sum_b partial[b * width + k] (added to out[k] if acc)
 __global__ void k_nn_sum_partials(const double *__restrict__ partial, int nblk, int width,
-                                  double *__restrict__ out) {
+                                  double *__restrict__ out, int acc) {
   __shared__ double red[4];
   const int k = blockIdx.x;
   double v = 0.0;
   for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(b) * width + k];
   v = block_sum_d(v, red);
-  if (threadIdx.x == 0) out[k] = v;
+  if (threadIdx.x == 0) out[k] = acc ? out[k] + v : v;
 }
 
 // per-sample ||v_b||^2 partials: partial[b * gridDim.x + blk]
@@ -590,6 +763,7 @@ struct NNState {
   double *grad = nullptr;        // FP64 gradient (2 * nparam reals)
   bool bf16 = true;              // activation storage
   int loss_kind = HISQ_NN_LOSS_SOLUTION;
+  int form = HISQ_NN_FORM_DIRECT;
   double loss_mass = 0.0;        // mass of M for the residual-norm loss
   // activation buffers (grow-only)
   void *act = nullptr;
@@ -630,7 +804,13 @@ int grow(hisq_ctx *ctx, void **p, size_t *cur, size_t bytes) {
   return HISQ_OK;
 }
 
+// Link copy the network reads: FP16 with BF16 activations (its rounding, 4.9e-4, is below
+// BF16's 3.9e-3, and it halves the link bytes), else FP32, else FP16.
 bool nn_links(hisq_ctx *ctx, int *prec) {
+  if (ctx->nn && ctx->nn->bf16 && ctx->links[HISQ_F16].base) {
+    *prec = HISQ_F16;
+    return true;
+  }
   if (ctx->links[HISQ_F32].base) {
     *prec = HISQ_F32;
     return true;
@@ -669,7 +849,7 @@ template <typename AT>
 int launch_stencil(hisq_ctx *ctx, const NNArgs &A, int prec, const void *in, void *out,
                    const float2 *a, bool adj) {
   const unsigned V = 2u * ctx->g.vh;
-  dim3 grid((V + kThreads - 1) / kThreads, A.batch);
+  dim3 grid((V + kThreads - 1) / kThreads * A.batch);
   const AT *i = static_cast<const AT *>(in);
   AT *o = static_cast<AT *>(out);
   if (prec == HISQ_F32) {
@@ -734,8 +914,10 @@ int act_bufs(hisq_ctx *ctx, int batch, bool train, ActBufs *b) {
   return HISQ_OK;
 }
 
+// N r for even-site vectors r32 ([b][3][V/2]); the readout goes to z32 on the even sites
+// ([b][3][V/2], the direct form) or on the full lattice ([b][3][V], full_out).
 template <typename AT>
-int forward_t(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, const ActBufs &b) {
+int forward_t(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, bool full_out, const ActBufs &b) {
   NNState *s = ctx->nn;
   int prec;
   nn_links(ctx, &prec);
@@ -743,27 +925,70 @@ int forward_t(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, const Ac
   const unsigned V = 2u * ctx->g.vh;
   const size_t ncols = size_t(batch) * 3 * V;
   dim3 gv((V + kThreads - 1) / kThreads, batch);
-  k_nn_embed<AT, false><<<gv, kThreads, 0, ctx->stream>>>(r32, static_cast<AT *>(b.phi[0]), A, s->theta);
+  k_nn_embed<AT, false><<<gv, kThreads, 0, ctx->stream>>>(r32, unsigned(ctx->g.vh), static_cast<AT *>(b.phi[0]),
+                                                          A, s->theta);
   LAUNCHCHK(ctx, "k_nn_embed");
   for (int l = 0; l < s->layers; ++l) {
     if (l >= 1) RETCHK(launch_mix(ctx, s, b.psi[l - 1], b.phi[l], ncols, s->theta + s->off_w[l], false));
     RETCHK(launch_stencil<AT>(ctx, A, prec, b.phi[l], b.psi[l], s->theta + s->off_a[l], false));
   }
-  dim3 ge((ctx->g.vh + kThreads - 1) / kThreads, batch);
-  k_nn_readout<AT><<<ge, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(b.psi[s->layers - 1]), z32, A,
-                                                    s->theta + s->off_out);
+  const unsigned vs = full_out ? V : unsigned(ctx->g.vh);
+  dim3 ge((vs + kThreads - 1) / kThreads, batch);
+  k_nn_readout<AT, false><<<ge, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(b.psi[s->layers - 1]), z32, vs,
+                                                           A, s->theta + s->off_out);
   LAUNCHCHK(ctx, "k_nn_readout");
   return HISQ_OK;
 }
 
-int forward(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, const ActBufs &b) {
-  return ctx->nn->bf16 ? forward_t<bf16>(ctx, batch, r32, z32, b) : forward_t<float>(ctx, batch, r32, z32, b);
+int forward(hisq_ctx *ctx, int batch, const float2 *r32, float2 *z32, bool full_out, const ActBufs &b) {
+  return ctx->nn->bf16 ? forward_t<bf16>(ctx, batch, r32, z32, full_out, b)
+                       : forward_t<float>(ctx, batch, r32, z32, full_out, b);
 }
 
-// Backward pass for one minibatch (after forward with train buffers): accumulates the FP64
-// Wirtinger gradient into s->grad (zeroed by the caller) and the loss partials.
+// N^dag u for full-lattice vectors u32 ([b][3][V]) into even-site vectors z32 ([b][3][V/2]): the
+// layers in reverse order with conjugated readout, adjoint stencils and W_l^dag mixings, ending
+// with the conjugated input weights.  t0 and t1 are two activation buffers.
 template <typename AT>
-int backward_t(hisq_ctx *ctx, int batch, const float2 *r32, const float2 *gz, const ActBufs &b,
+int adjoint_t(hisq_ctx *ctx, int batch, const float2 *u32, float2 *z32, void *t0, void *t1) {
+  NNState *s = ctx->nn;
+  int prec;
+  nn_links(ctx, &prec);
+  const NNArgs A = nn_args(ctx, batch, prec);
+  const unsigned V = 2u * ctx->g.vh;
+  const size_t ncols = size_t(batch) * 3 * V;
+  dim3 gv((V + kThreads - 1) / kThreads, batch);
+  k_nn_embed<AT, true><<<gv, kThreads, 0, ctx->stream>>>(u32, V, static_cast<AT *>(t0), A, s->theta + s->off_out);
+  LAUNCHCHK(ctx, "k_nn_embed");
+  for (int l = s->layers - 1; l >= 0; --l) {
+    RETCHK(launch_stencil<AT>(ctx, A, prec, t0, t1, s->theta + s->off_a[l], true));
+    if (l >= 1) RETCHK(launch_mix(ctx, s, t1, t0, ncols, s->theta + s->off_w[l], true));
+  }
+  dim3 ge((ctx->g.vh + kThreads - 1) / kThreads, batch);
+  k_nn_readout<AT, true><<<ge, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(t1), z32, unsigned(ctx->g.vh),
+                                                          A, s->theta);
+  LAUNCHCHK(ctx, "k_nn_readout");
+  return HISQ_OK;
+}
+
+int adjoint(hisq_ctx *ctx, int batch, const float2 *u32, float2 *z32, void *t0, void *t1) {
+  return ctx->nn->bf16 ? adjoint_t<bf16>(ctx, batch, u32, z32, t0, t1)
+                       : adjoint_t<float>(ctx, batch, u32, z32, t0, t1);
+}
+
+// complex G_W[o][i] += (Q[2o][2i] + Q[2o+1][2i+1]) + i (Q[2o+1][2i] - Q[2o][2i+1])
+__global__ void k_nn_assemble_w(const double *__restrict__ Q, double *__restrict__ gw) {
+  const int t = threadIdx.x;
+  if (t >= NC * NC) return;
+  const int o = t / NC, i = t % NC;
+  gw[2 * t] += Q[(2 * o) * NR + 2 * i] + Q[(2 * o + 1) * NR + 2 * i + 1];
+  gw[2 * t + 1] += Q[(2 * o + 1) * NR + 2 * i] - Q[(2 * o) * NR + 2 * i + 1];
+}
+
+// Backward pass after forward_t with the train buffers on the input x32: adds to s->grad the
+// Wirtinger gradient of Re<gz, N x>, with gz the output gradient on the even sites ([b][3][V/2],
+// gvs = V/2; the direct form) or on the full lattice ([b][3][V], gvs = V).
+template <typename AT>
+int backward_t(hisq_ctx *ctx, int batch, const float2 *x32, const float2 *gz, unsigned gvs, const ActBufs &b,
                double *partial, size_t partial_cap, double *red) {
   NNState *s = ctx->nn;
   int prec;
@@ -775,14 +1000,15 @@ int backward_t(hisq_ctx *ctx, int batch, const float2 *r32, const float2 *gz, co
   if (size_t(nblk) * 9 * 2 * NC > partial_cap || size_t(nblk) * NR * NR > partial_cap)
     return set_err(ctx, HISQ_ERR_STATE, "network partial buffer too small");
   // W_out: G[c] = sum conj(psi_L[c]) gz
-  k_nn_chan_dot<AT, true><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(b.psi[s->layers - 1]), gz, A, partial);
+  k_nn_chan_dot<AT, true><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(b.psi[s->layers - 1]), gz,
+                                                             gvs, A, partial);
   LAUNCHCHK(ctx, "k_nn_chan_dot");
-  k_nn_sum_partials<<<2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 2 * NC, s->grad + 2 * s->off_out);
+  k_nn_sum_partials<<<2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 2 * NC, s->grad + 2 * s->off_out, 1);
   LAUNCHCHK(ctx, "k_nn_sum_partials");
-  // g_psi_L = conj(W_out) (x) E(gz)
+  // g_psi_L = conj(W_out) (x) gz
   dim3 gv((V + kThreads - 1) / kThreads, batch);
   void *gpsi = b.g0, *gphi = b.g1;
-  k_nn_embed<AT, true><<<gv, kThreads, 0, ctx->stream>>>(gz, static_cast<AT *>(gpsi), A, s->theta + s->off_out);
+  k_nn_embed<AT, true><<<gv, kThreads, 0, ctx->stream>>>(gz, gvs, static_cast<AT *>(gpsi), A, s->theta + s->off_out);
   LAUNCHCHK(ctx, "k_nn_embed");
   for (int l = s->layers - 1; l >= 0; --l) {
     // stencil weights
@@ -793,41 +1019,43 @@ int backward_t(hisq_ctx *ctx, int batch, const float2 *r32, const float2 *gz, co
       k_nn_stencil_wgrad<AT, __half2><<<nblk, kThreads, 0, ctx->stream>>>(
           A, static_cast<const AT *>(b.phi[l]), static_cast<const AT *>(gpsi), partial);
     LAUNCHCHK(ctx, "k_nn_stencil_wgrad");
-    k_nn_sum_partials<<<9 * 2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 9 * 2 * NC, s->grad + 2 * s->off_a[l]);
+    k_nn_sum_partials<<<9 * 2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 9 * 2 * NC,
+                                                               s->grad + 2 * s->off_a[l], 1);
     LAUNCHCHK(ctx, "k_nn_sum_partials");
     // g_phi = S^dag g_psi
     RETCHK(launch_stencil<AT>(ctx, A, prec, gpsi, gphi, s->theta + s->off_a[l], true));
     if (l >= 1) {
-      // W_l: Q = sum g_phi_real psi_{l-1}_real^T, assembled into complex G by nn_assemble_w
+      // W_l: Q = sum g_phi_real psi_{l-1}_real^T, assembled into the complex gradient
       k_nn_mix_wgrad<AT><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(gphi),
                                                              static_cast<const AT *>(b.psi[l - 1]), ncols, partial);
       LAUNCHCHK(ctx, "k_nn_mix_wgrad");
-      k_nn_sum_partials<<<NR * NR, kThreads, 0, ctx->stream>>>(partial, nblk, NR * NR, red + (l - 1) * NR * NR);
+      k_nn_sum_partials<<<NR * NR, kThreads, 0, ctx->stream>>>(partial, nblk, NR * NR, red, 0);
       LAUNCHCHK(ctx, "k_nn_sum_partials");
+      k_nn_assemble_w<<<1, 64, 0, ctx->stream>>>(red, s->grad + 2 * s->off_w[l]);
+      LAUNCHCHK(ctx, "k_nn_assemble_w");
       // g_psi_{l-1} = W_l^dag g_phi
       RETCHK(launch_mix(ctx, s, gphi, gpsi, ncols, s->theta + s->off_w[l], true));
     } else {
-      // W_in: G[c] = sum conj(r) g_phi_1[c]
-      k_nn_chan_dot<AT, false><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(gphi), r32, A, partial);
+      // W_in: G[c] = sum conj(x) g_phi_1[c] over the even sites
+      k_nn_chan_dot<AT, false><<<nblk, kThreads, 0, ctx->stream>>>(static_cast<const AT *>(gphi), x32,
+                                                                  unsigned(ctx->g.vh), A, partial);
       LAUNCHCHK(ctx, "k_nn_chan_dot");
-      k_nn_sum_partials<<<2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 2 * NC, s->grad);
+      k_nn_sum_partials<<<2 * NC, kThreads, 0, ctx->stream>>>(partial, nblk, 2 * NC, s->grad, 1);
       LAUNCHCHK(ctx, "k_nn_sum_partials");
     }
   }
   return HISQ_OK;
 }
 
-// complex G_W[o][i] = (Q[2o][2i] + Q[2o+1][2i+1]) + i (Q[2o+1][2i] - Q[2o][2i+1])
-__global__ void k_nn_assemble_w(const double *__restrict__ Q, double *__restrict__ gw) {
-  const int t = threadIdx.x;
-  if (t >= NC * NC) return;
-  const int o = t / NC, i = t % NC;
-  gw[2 * t] = Q[(2 * o) * NR + 2 * i] + Q[(2 * o + 1) * NR + 2 * i + 1];
-  gw[2 * t + 1] = Q[(2 * o + 1) * NR + 2 * i] - Q[(2 * o) * NR + 2 * i + 1];
+int backward(hisq_ctx *ctx, int batch, const float2 *x32, const float2 *gz, unsigned gvs, const ActBufs &b,
+             double *partial, size_t partial_cap, double *red) {
+  return ctx->nn->bf16 ? backward_t<bf16>(ctx, batch, x32, gz, gvs, b, partial, partial_cap, red)
+                       : backward_t<float>(ctx, batch, x32, gz, gvs, b, partial, partial_cap, red);
 }
 
 struct Scratch {
   float2 *r32, *y32, *z32, *gz, *w32, *t32, *gw;
+  float2 *u, *ng;   // full-lattice N r and N G of the Gram form ([b][3][V])
   double *ynorm2, *partial, *red, *loss;
   size_t partial_cap;
 };
@@ -836,33 +1064,41 @@ int scratch(hisq_ctx *ctx, int batch, Scratch *sc) {
   NNState *s = ctx->nn;
   const size_t vec = size_t(batch) * 3 * ctx->g.vh * sizeof(float2);
   const size_t partial_cap = 1024 * NR * NR;  // doubles: >= 1024 * 9 * 2C, 1024 * 256, 256 * batch
-  const size_t bytes = 7 * vec + (batch + partial_cap + 8 * NR * NR + 64) * sizeof(double) + 4096;
+  const size_t bytes = 11 * vec + (batch + partial_cap + NR * NR + 64) * sizeof(double) + 4096;
   RETCHK(grow(ctx, &s->scratch, &s->scratch_bytes, bytes));
   char *p = static_cast<char *>(s->scratch);
-  sc->r32 = reinterpret_cast<float2 *>(p);
-  sc->y32 = reinterpret_cast<float2 *>(p + vec);
-  sc->z32 = reinterpret_cast<float2 *>(p + 2 * vec);
-  sc->gz = reinterpret_cast<float2 *>(p + 3 * vec);
-  sc->w32 = reinterpret_cast<float2 *>(p + 4 * vec);
-  sc->t32 = reinterpret_cast<float2 *>(p + 5 * vec);
-  sc->gw = reinterpret_cast<float2 *>(p + 6 * vec);
-  double *d = reinterpret_cast<double *>(p + 7 * vec);
+  float2 *v[7];
+  for (int i = 0; i < 7; ++i) v[i] = reinterpret_cast<float2 *>(p + i * vec);
+  sc->r32 = v[0];
+  sc->y32 = v[1];
+  sc->z32 = v[2];
+  sc->gz = v[3];
+  sc->w32 = v[4];
+  sc->t32 = v[5];
+  sc->gw = v[6];
+  sc->u = reinterpret_cast<float2 *>(p + 7 * vec);
+  sc->ng = reinterpret_cast<float2 *>(p + 9 * vec);
+  double *d = reinterpret_cast<double *>(p + 11 * vec);
   sc->ynorm2 = d;
   sc->partial = d + batch;
   sc->partial_cap = partial_cap;
   sc->red = sc->partial + partial_cap;
-  sc->loss = sc->red + 8 * NR * NR;
+  sc->loss = sc->red + NR * NR;
   return HISQ_OK;
 }
 
+// Loss and gradient of one minibatch.  Direct form: z = R_even N r, one forward and one backward
+// pass.  Gram form: u = N r, z = N^dag u; with G the loss gradient with respect to z,
+// dL = Re<u, dN G> + Re<N G, dN r>, i.e. two backward passes (input G with output gradient u,
+// input r with output gradient N G).
 int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f64_io, double *loss_dev) {
   NNState *s = ctx->nn;
   Scratch sc;
   RETCHK(scratch(ctx, batch, &sc));
-  if (s->layers - 1 > 8) return set_err(ctx, HISQ_ERR_ARG, "too many layers");
   ActBufs b;
   RETCHK(act_bufs(ctx, batch, true, &b));
   const size_t len = size_t(batch) * 3 * ctx->g.vh;
+  const unsigned V = 2u * ctx->g.vh;
   const float2 *r32 = static_cast<const float2 *>(r), *y32 = static_cast<const float2 *>(y);
   if (f64_io) {
     k_to_c64<<<1024, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(r), sc.r32, len);
@@ -872,6 +1108,7 @@ int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f
     y32 = sc.y32;
   }
   const bool resid = s->loss_kind == HISQ_NN_LOSS_RESIDUAL;
+  const bool gram = s->form == HISQ_NN_FORM_GRAM;
   // ||t_b||^2 in FP64 of the FP32 vector the loss compares against (y, or r for the residual loss)
   const float2 *target = resid ? r32 : y32;
   {
@@ -881,12 +1118,16 @@ int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f
     k_nn_sum_rows<<<batch, kThreads, 0, ctx->stream>>>(sc.partial, nblk, sc.ynorm2);
     LAUNCHCHK(ctx, "k_nn_sum_rows");
   }
-  RETCHK(forward(ctx, batch, r32, sc.z32, b));
+  if (gram) {
+    RETCHK(forward(ctx, batch, r32, sc.u, true, b));
+    RETCHK(adjoint(ctx, batch, sc.u, sc.z32, b.g0, b.g1));
+  } else {
+    RETCHK(forward(ctx, batch, r32, sc.z32, false, b));
+  }
   const int lblk = 256;
   dim3 gl(lblk, batch);
-  int mprec = 0;
   if (resid) {  // w = M z; gradient w.r.t. w, then g_z = M g_w (M is Hermitian)
-    mprec = ctx->links[HISQ_F32].base ? HISQ_F32 : HISQ_F16;
+    const int mprec = ctx->links[HISQ_F32].base ? HISQ_F32 : HISQ_F16;
     const double m2 = s->loss_mass * s->loss_mass;
     RETCHK(launch_dslash(ctx, 1, mprec, batch, sc.z32, sc.t32, false, 0.0, nullptr, nullptr, nullptr));
     RETCHK(launch_dslash(ctx, 0, mprec, batch, sc.t32, sc.w32, true, m2, sc.z32, nullptr, nullptr));
@@ -898,16 +1139,16 @@ int nn_batch_grad(hisq_ctx *ctx, int batch, const void *r, const void *y, bool f
     k_nn_loss<<<gl, kThreads, 0, ctx->stream>>>(sc.z32, y32, sc.ynorm2, sc.gz, unsigned(3 * ctx->g.vh), batch, sc.partial);
     LAUNCHCHK(ctx, "k_nn_loss");
   }
-  k_nn_sum_partials<<<1, kThreads, 0, ctx->stream>>>(sc.partial, lblk * batch, 1, loss_dev);
+  k_nn_sum_partials<<<1, kThreads, 0, ctx->stream>>>(sc.partial, lblk * batch, 1, loss_dev, 0);
   LAUNCHCHK(ctx, "k_nn_sum_partials");
   HIPCHK(ctx, hipMemsetAsync(s->grad, 0, size_t(2) * s->nparam * sizeof(double), ctx->stream));
-  if (s->bf16)
-    RETCHK(backward_t<bf16>(ctx, batch, r32, sc.gz, b, sc.partial, sc.partial_cap, sc.red));
-  else
-    RETCHK(backward_t<float>(ctx, batch, r32, sc.gz, b, sc.partial, sc.partial_cap, sc.red));
-  for (int l = 1; l < s->layers; ++l) {
-    k_nn_assemble_w<<<1, 64, 0, ctx->stream>>>(sc.red + (l - 1) * NR * NR, s->grad + 2 * s->off_w[l]);
-    LAUNCHCHK(ctx, "k_nn_assemble_w");
+  if (gram) {
+    RETCHK(forward(ctx, batch, sc.gz, sc.ng, true, b));
+    RETCHK(backward(ctx, batch, sc.gz, sc.u, V, b, sc.partial, sc.partial_cap, sc.red));
+    RETCHK(forward(ctx, batch, r32, sc.u, true, b));  // caches for input r (u is no longer needed)
+    RETCHK(backward(ctx, batch, r32, sc.ng, V, b, sc.partial, sc.partial_cap, sc.red));
+  } else {
+    RETCHK(backward(ctx, batch, r32, sc.gz, unsigned(ctx->g.vh), b, sc.partial, sc.partial_cap, sc.red));
   }
   return HISQ_OK;
 }
@@ -1031,6 +1272,15 @@ extern "C" int hisq_nn_set_loss(hisq_ctx *ctx, int kind, double mass) {
   return HISQ_OK;
 }
 
+extern "C" int hisq_nn_set_form(hisq_ctx *ctx, int form) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_set_form: no network");
+  if (form != HISQ_NN_FORM_DIRECT && form != HISQ_NN_FORM_GRAM)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_set_form: bad form %d", form);
+  ctx->nn->form = form;
+  return HISQ_OK;
+}
+
 extern "C" int hisq_nn_set_precision(hisq_ctx *ctx, int bf16_storage) {
   if (!ctx) return HISQ_ERR_ARG;
   if (!ctx->nn) return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_set_precision: no network");
@@ -1038,11 +1288,96 @@ extern "C" int hisq_nn_set_precision(hisq_ctx *ctx, int bf16_storage) {
   return HISQ_OK;
 }
 
-// z = P r for n vectors (precision of r and z: HISQ_F64 complex128 or HISQ_F32 complex64)
+// ---- fused inference ----
+template <typename AT, typename LT>
+int launch_layer_t(hisq_ctx *ctx, const FusedArgs &F, bool adj, bool in_vec, bool out_vec, int batch) {
+  dim3 grid((F.out_sites + kThreads - 1) / kThreads * batch);
+  const int key = (adj ? 4 : 0) | (in_vec ? 2 : 0) | (out_vec ? 1 : 0);
+  switch (key) {
+    case 0: k_nn_layer<AT, LT, false, false, false><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    case 1: k_nn_layer<AT, LT, false, false, true><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    case 2: k_nn_layer<AT, LT, false, true, false><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    case 3: k_nn_layer<AT, LT, false, true, true><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    case 4: k_nn_layer<AT, LT, true, false, false><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    case 5: k_nn_layer<AT, LT, true, false, true><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    case 6: k_nn_layer<AT, LT, true, true, false><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+    default: k_nn_layer<AT, LT, true, true, true><<<grid, kThreads, 0, ctx->stream>>>(F); break;
+  }
+  LAUNCHCHK(ctx, "k_nn_layer");
+  return HISQ_OK;
+}
+
+int launch_layer(hisq_ctx *ctx, const FusedArgs &F, bool adj, bool in_vec, bool out_vec, int batch,
+                 int prec) {
+  if (ctx->nn->bf16)
+    return prec == HISQ_F32 ? launch_layer_t<bf16, float2>(ctx, F, adj, in_vec, out_vec, batch)
+                            : launch_layer_t<bf16, __half2>(ctx, F, adj, in_vec, out_vec, batch);
+  return prec == HISQ_F32 ? launch_layer_t<float, float2>(ctx, F, adj, in_vec, out_vec, batch)
+                          : launch_layer_t<float, __half2>(ctx, F, adj, in_vec, out_vec, batch);
+}
+
+// N r (forward) for even-site r32 into out32: on the even sites ([b][3][V/2]) or the full lattice
+// ([b][3][V], full_out).  One fused layer kernel per layer; t0, t1: two activation buffers.
+int forward_infer(hisq_ctx *ctx, int batch, const float2 *r32, float2 *out32, bool full_out, void *t0, void *t1) {
+  NNState *s = ctx->nn;
+  int prec;
+  nn_links(ctx, &prec);
+  const unsigned V = 2u * ctx->g.vh;
+  void *buf[2] = {t0, t1};
+  for (int l = 0; l < s->layers; ++l) {
+    FusedArgs F{};
+    F.A = nn_args(ctx, batch, prec);
+    const bool in_vec = l == 0, out_vec = l == s->layers - 1;
+    F.in = in_vec ? static_cast<const void *>(r32) : buf[(l - 1) & 1];
+    F.out = out_vec ? static_cast<void *>(out32) : buf[l & 1];
+    F.a = s->theta + s->off_a[l];
+    F.w = out_vec ? nullptr : s->theta + s->off_w[l + 1];
+    F.win = s->theta;
+    F.wout = s->theta + s->off_out;
+    F.vin_sites = unsigned(ctx->g.vh);
+    F.out_sites = out_vec && !full_out ? unsigned(ctx->g.vh) : V;
+    RETCHK(launch_layer(ctx, F, false, in_vec, out_vec, batch, prec));
+  }
+  return HISQ_OK;
+}
+
+// N^dag u for full-lattice u32 ([b][3][V]) into even-site z32 ([b][3][V/2]).
+int adjoint_infer(hisq_ctx *ctx, int batch, const float2 *u32, float2 *z32, void *t0, void *t1) {
+  NNState *s = ctx->nn;
+  int prec;
+  nn_links(ctx, &prec);
+  const unsigned V = 2u * ctx->g.vh;
+  void *buf[2] = {t0, t1};
+  int k = 0;
+  for (int l = s->layers - 1; l >= 0; --l, ++k) {
+    FusedArgs F{};
+    F.A = nn_args(ctx, batch, prec);
+    const bool in_vec = l == s->layers - 1, out_vec = l == 0;
+    F.in = in_vec ? static_cast<const void *>(u32) : buf[(k - 1) & 1];
+    F.out = out_vec ? static_cast<void *>(z32) : buf[k & 1];
+    F.a = s->theta + s->off_a[l];
+    F.w = out_vec ? nullptr : s->theta + s->off_w[l];
+    F.mix_conjt = 1;
+    F.win = s->theta + s->off_out;
+    F.in_conj = 1;
+    F.wout = s->theta;
+    F.out_conj = 1;
+    F.vin_sites = V;
+    F.out_sites = out_vec ? unsigned(ctx->g.vh) : V;
+    RETCHK(launch_layer(ctx, F, true, in_vec, out_vec, batch, prec));
+  }
+  return HISQ_OK;
+}
+
+// z = P r for n vectors in FP32 (direct: R_even N r; Gram: N^dag N r)
 int nn_apply_internal(hisq_ctx *ctx, int n, const float2 *r32, float2 *z32) {
   ActBufs b;
   RETCHK(act_bufs(ctx, n, false, &b));
-  return forward(ctx, n, r32, z32, b);
+  if (ctx->nn->form != HISQ_NN_FORM_GRAM) return forward_infer(ctx, n, r32, z32, false, b.phi[0], b.psi[0]);
+  Scratch sc;
+  RETCHK(scratch(ctx, n, &sc));
+  RETCHK(forward_infer(ctx, n, r32, sc.u, true, b.phi[0], b.psi[0]));
+  return adjoint_infer(ctx, n, sc.u, z32, b.phi[0], b.psi[0]);
 }
 
 extern "C" int hisq_nn_apply(hisq_ctx *ctx, int n, int prec_io, const void *r, void *z) {
@@ -1133,7 +1468,7 @@ extern "C" int hisq_nn_save(hisq_ctx *ctx, const char *path) {
   RETCHK(hisq_nn_get_params(ctx, w.data(), nreal));
   FILE *f = fopen(path, "wb");
   if (!f) return set_err(ctx, HISQ_ERR_IO, "hisq_nn_save: cannot open %s", path);
-  const int hdr[4] = {0x51534948 /* "HISQ" */, 1, ctx->nn->layers, NC};
+  const int hdr[5] = {0x51534948 /* "HISQ" */, 2, ctx->nn->layers, NC, ctx->nn->form};
   bool ok = fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(w.data(), sizeof(double), nreal, f) == size_t(nreal);
   ok = (fclose(f) == 0) && ok;
   return ok ? HISQ_OK : set_err(ctx, HISQ_ERR_IO, "hisq_nn_save: write failed");
@@ -1144,9 +1479,12 @@ extern "C" int hisq_nn_load(hisq_ctx *ctx, const char *path) {
   if (!path) return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_load: null path");
   FILE *f = fopen(path, "rb");
   if (!f) return set_err(ctx, HISQ_ERR_IO, "hisq_nn_load: cannot open %s", path);
-  int hdr[4];
-  if (fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != 0x51534948 || hdr[1] != 1 || hdr[3] != NC ||
-      hdr[2] < 1 || hdr[2] > 8) {
+  int hdr[5] = {0, 0, 0, 0, HISQ_NN_FORM_DIRECT};  // version 1 files have no form field
+  bool hdr_ok = fread(hdr, sizeof(int), 4, f) == 4 && hdr[0] == 0x51534948 && (hdr[1] == 1 || hdr[1] == 2) &&
+                hdr[3] == NC && hdr[2] >= 1 && hdr[2] <= 8;
+  if (hdr_ok && hdr[1] == 2)
+    hdr_ok = fread(hdr + 4, sizeof(int), 1, f) == 1 && (hdr[4] == HISQ_NN_FORM_DIRECT || hdr[4] == HISQ_NN_FORM_GRAM);
+  if (!hdr_ok) {
     fclose(f);
     return set_err(ctx, HISQ_ERR_IO, "hisq_nn_load: %s is not a network file", path);
   }
@@ -1156,6 +1494,7 @@ extern "C" int hisq_nn_load(hisq_ctx *ctx, const char *path) {
   fclose(f);
   if (!ok) return set_err(ctx, HISQ_ERR_IO, "hisq_nn_load: %s is truncated", path);
   if (!ctx->nn || ctx->nn->layers != hdr[2]) RETCHK(hisq_nn_init(ctx, hdr[2], NC, 1));
+  ctx->nn->form = hdr[4];
   return hisq_nn_set_params(ctx, w.data(), nreal);
 }
 
@@ -1270,6 +1609,7 @@ int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
   RETCHK(cg_finish(ctx, mass, n, b, x, prm->tol, S, hS, partial, st, &ok));
   int fcg_iters[HISQ_MAX_RHS];
   for (int i = 0; i < n; ++i) fcg_iters[i] = hS->iters[i];
+  const long long fcg_site_rhs = st ? st->dslash_site_rhs : 0;
   bool need = false;
   for (int i = 0; i < n; ++i) {
     const double res = hS->bnorm2[i] > 0 ? std::sqrt(hS->rr_true[i] / hS->bnorm2[i]) : 0.0;
@@ -1298,6 +1638,7 @@ int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
       for (int i = 0; i < n; ++i) st->fell_back[i] = fell[i];
     st->total_iters = total;
     st->reliable_updates = reps + (need ? st->reliable_updates : 0);
+    if (need) st->dslash_site_rhs += fcg_site_rhs;
   }
   if (!ok) return set_err(ctx, HISQ_ERR_NOCONV, "hisq_cg_mrhs: some rhs missed tol %.3g", prm->tol);
   return HISQ_OK;

@@ -35,6 +35,7 @@ HISQ_LINKS_F64, HISQ_LINKS_F32, HISQ_LINKS_F16, HISQ_LINKS_ALL = 1, 2, 4, 7
 HISQ_CG_F64, HISQ_CG_MIXED, HISQ_FCG_NN = 0, 1, 2
 HISQ_MAX_RHS = 64
 HISQ_NN_LOSS_SOLUTION, HISQ_NN_LOSS_RESIDUAL = 0, 1
+HISQ_NN_FORM_DIRECT, HISQ_NN_FORM_GRAM = 0, 1
 
 _ERR_NAMES = {
     HISQ_ERR_ARG: "HISQ_ERR_ARG", HISQ_ERR_STATE: "HISQ_ERR_STATE", HISQ_ERR_HIP: "HISQ_ERR_HIP",
@@ -127,6 +128,7 @@ def _load():
         "hisq_nn_loss_grad": (cint, [vp, cint, vp, vp, dp, dp]),
         "hisq_nn_train": (cint, [vp, cint, vp, vp, cint, cint, cd, ctypes.c_ulonglong, dp]),
         "hisq_nn_set_precision": (cint, [vp, cint]),
+        "hisq_nn_set_form": (cint, [vp, cint]),
         "hisq_nn_set_loss": (cint, [vp, cint, cd]),
         "hisq_nn_harvest": (cint, [vp, cd, cint, vp, cd, cint, cint, vp, vp, ip]),
         "hisq_nn_save": (cint, [vp, ctypes.c_char_p]),

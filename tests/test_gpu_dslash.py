@@ -200,17 +200,36 @@ def test_full_size_32c8_sampled_sites():
 
 
 ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
-            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3) for xm in (0, 1)
+            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3) for xm in (0, 1, 2)
                for nt in (0, 1)])
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4)])
+def _cfg_valid(prec, cfg, dims):
+    """The launch rules of the header: FP64 has no 16-rhs tile and no LDS form; the 16-wave LDS
+    form takes at most 2 rhs per thread; the z-slab map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0,
+    the y-slab map (Lx/2)*Ly % 512 == 0."""
+    rt, spb, nt, lds, xm = cfg
+    plane = dims[0] // 2 * dims[1]
+    if prec == hisq.HISQ_F64 and (rt == 16 or lds):
+        return False
+    if lds == 3 and rt > 2:
+        return False
+    if xm == 1 and not (plane % 64 == 0 and dims[2] % 8 == 0):
+        return False
+    if xm == 2 and plane % 512 != 0:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4), (16, 64, 4, 4)])
 @pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
                                         (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14)])
 def test_every_launch_config_bit_identical(prec, recon, dims):
-    """All register tiles, workgroup shapes, cache hints and the LDS-staged form give the same
-    bits, for the plain half Dslash and for the fused M operator (including its FP64 <p, Mp>
-    reduction), and the autotuned choice is one of them.  (16, 8, 8, 4) admits the z-slab XCD map."""
+    """All register tiles, workgroup shapes, cache hints, the LDS-staged form and the XCD maps give
+    the same bits, for the plain half Dslash and for the fused M operator (including its FP64
+    <p, Mp> reduction), and the autotuned choice is one of them.  Exactly the configurations the
+    header rules out are refused.  (16, 8, 8, 4) admits the z-slab XCD map, (16, 64, 4, 4) the
+    y-slab map."""
     n, mass = 11, 0.1
     lat, fat, naik = make_lattice(dims, 120, recon=recon)
     dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
@@ -222,12 +241,11 @@ def test_every_launch_config_bit_identical(prec, recon, dims):
     for cfg in ALL_CFGS:
         try:
             hisq.hisq_set_launch(lat.ctx, prec, n, cfg)
-        except hisq.HisqError as e:  # FP64 rt 16, FP64 LDS form, LDS beyond the device limit,
-            assert e.code == hisq.HISQ_ERR_ARG  # or a z-slab map the lattice does not admit
-            assert (prec == hisq.HISQ_F64 and (cfg[0] == 16 or cfg[3])) or cfg[3]
-            assert not (dims == (16, 8, 8, 4) and cfg[4] and prec == hisq.HISQ_F16 and
-                        not (cfg[3] == 3 and cfg[0] == 4))  # 16-wave LDS form takes rt <= 2
+        except hisq.HisqError as e:
+            assert e.code == hisq.HISQ_ERR_ARG
+            assert not _cfg_valid(prec, cfg, dims), cfg
             continue
+        assert _cfg_valid(prec, cfg, dims), cfg
         tried += 1
         out = lat.dslash(1, prec, v)
         m, pq = lat.apply_m(prec, mass, v, with_pq=True)

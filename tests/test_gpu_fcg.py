@@ -112,12 +112,17 @@ def test_harvest_pairs_are_exact():
     lat.close()
 
 
-@pytest.mark.parametrize("loss_kind", [hisq.HISQ_NN_LOSS_SOLUTION, hisq.HISQ_NN_LOSS_RESIDUAL])
-def test_trained_network_gain(loss_kind):
+@pytest.mark.parametrize("form,loss_kind", [
+    (hisq.HISQ_NN_FORM_DIRECT, hisq.HISQ_NN_LOSS_SOLUTION),
+    (hisq.HISQ_NN_FORM_DIRECT, hisq.HISQ_NN_LOSS_RESIDUAL),
+    (hisq.HISQ_NN_FORM_GRAM, hisq.HISQ_NN_LOSS_RESIDUAL),
+])
+def test_trained_network_gain(form, loss_kind):
     """Train the network on harvested pairs and compare FCG iterations with the untrained
-    (identity) network, i.e. plain CG.  The residual-norm loss must give fewer iterations; the
-    solution-norm loss is reported (a 4-hop linear map cannot represent the low modes that
-    dominate M^-1 r, and that loss weights them most)."""
+    (identity) network, i.e. plain CG.  The Gram form (Hermitian positive semi-definite) trained
+    on the residual-norm loss must need fewer iterations and never fall back.  The direct form is
+    reported only: it is not Hermitian, which FCG(1) tolerates badly, and with the solution-norm
+    loss it is fitted to the low modes that dominate M^-1 r, which a 4-hop map cannot represent."""
     dims, mass, tol = (8, 8, 8, 8), 0.05, 1e-8
     lat, fat, naik = make_lattice(dims, 408)
     lib = hisq.library()
@@ -130,10 +135,13 @@ def test_trained_network_gain(loss_kind):
                                              hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
     assert lib.hisq_nn_init(lat.ctx, L, 8, 3) == 0
     assert lib.hisq_nn_set_loss(lat.ctx, loss_kind, mass) == 0
-    hist = (ctypes.c_double * 30)()
-    hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y), 30, 16,
-                                           3e-3, 11, hist))
-    print("training loss:", [f"{v:.3f}" for v in list(hist)[::5]], f"final {hist[29]:.3f}")
+    assert lib.hisq_nn_set_form(lat.ctx, form) == 0
+    epochs = 30
+    hist = (ctypes.c_double * epochs)()
+    lr = 1e-2 if form == hisq.HISQ_NN_FORM_GRAM else 3e-3
+    hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y), epochs, 16,
+                                           lr, 11, hist))
+    print("training loss:", [f"{v:.3f}" for v in list(hist)[::5]], f"final {hist[epochs - 1]:.3f}")
     bt = torch.from_numpy(synth.sources(dims, 8, 410)).to(DEV)
     xt, ti = lat.cg(mass, bt, kind=hisq.HISQ_FCG_NN, tol=tol, link_prec=hisq.HISQ_F32)
     _set(lib, lat.ctx, _identity_params(lib, lat.ctx))
@@ -141,11 +149,11 @@ def test_trained_network_gain(loss_kind):
     assert ti["rc"] == 0 and ui["rc"] == 0
     res = oracle.true_residual(fat, naik, xt.cpu().numpy(), bt.cpu().numpy(), dims, mass)
     assert np.all(res <= tol)
-    print(f"loss {loss_kind}: trained FCG iters {np.mean(ti['iters']):.1f} ({ti['seconds']:.3f}s, "
+    print(f"form {form} loss {loss_kind}: trained FCG iters {np.mean(ti['iters']):.1f} ({ti['seconds']:.3f}s, "
           f"fell back {sum(ti['fell_back'])}); identity iters {np.mean(ui['iters']):.1f} "
           f"({ui['seconds']:.3f}s)")
-    assert hist[29] < hist[0]
-    if loss_kind == hisq.HISQ_NN_LOSS_RESIDUAL:
+    assert hist[epochs - 1] < hist[0]
+    if form == hisq.HISQ_NN_FORM_GRAM:
         assert sum(ti["fell_back"]) == 0
-        assert np.mean(ti["iters"]) < np.mean(ui["iters"])
+        assert np.mean(ti["iters"]) < 0.8 * np.mean(ui["iters"])
     lat.close()

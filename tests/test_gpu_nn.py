@@ -1,5 +1,6 @@
 """GPU parity of the learned preconditioner's forward pass, loss and Wirtinger gradients against
-the FP64 network oracle, plus gauge covariance, training and save/load on the GPU.
+the FP64 network oracle (direct form R_even N and Gram form N^dag N), plus gauge covariance,
+training and save/load on the GPU.
 
 Tolerances: FP32 activation storage relative L2 1e-5 (forward) and 1e-4 (gradient vector);
 BF16 storage (MFMA channel mixing) relative L2 5e-2 and cosine similarity >= 0.999.
@@ -160,4 +161,73 @@ def test_training_reduces_loss_and_save_load(tmp_path):
     w2 = (hisq.ctypes.c_double * (2 * n))()
     hisq._check(lat.ctx, lib.hisq_nn_get_params(lat.ctx, w2, 2 * n))
     assert list(w1) == list(w2)
+    lat.close()
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_gram_apply_matches_oracle(bf16):
+    lat, fat, naik = make_lattice(DIMS, 320)
+    _init(lat, bf16)
+    th = _theta(321)
+    _set(lat, th)
+    assert hisq.library().hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM) == 0
+    r = synth.sources(DIMS, 3, 322)
+    z = _apply(lat, torch.from_numpy(r).to(DEV))
+    ref = np.stack([onn.apply(th, fat, r[i], DIMS, 8, L, "gram") for i in range(3)])
+    err = rel_l2(z, ref)
+    print(f"NN Gram apply bf16={bf16}: rel L2 {err:.3g}, cosine {_cos(z, ref):.6f}")
+    if bf16:
+        assert err <= 5e-2 and _cos(z, ref) >= 0.999
+    else:
+        assert err <= 1e-5
+    lat.close()
+
+
+@pytest.mark.parametrize("bf16,kind", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_gram_loss_and_gradient_match_oracle(bf16, kind):
+    lat, fat, naik = make_lattice(DIMS, 323)
+    _init(lat, bf16)
+    th = _theta(324, scale=0.3)
+    _set(lat, th)
+    mass = 0.3
+    lib = hisq.library()
+    assert lib.hisq_nn_set_loss(lat.ctx, kind, mass) == 0
+    assert lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM) == 0
+    r = synth.sources(DIMS, 2, 325)
+    y = synth.sources(DIMS, 2, 326)
+    loss = hisq.ctypes.c_double()
+    grad = (hisq.ctypes.c_double * (2 * th.size))()
+    tr, ty = torch.from_numpy(r).to(DEV), torch.from_numpy(y).to(DEV)
+    hisq._check(lat.ctx, lib.hisq_nn_loss_grad(lat.ctx, 2, hisq._ptr(tr), hisq._ptr(ty), hisq.ctypes.byref(loss), grad))
+    g = np.array(grad[0::2]) + 1j * np.array(grad[1::2])
+    lref, gref = onn.gram_loss_and_grad(th, fat, r, y, DIMS, 8, L, kind=("solution", "residual")[kind],
+                                        naik=naik, mass=mass)
+    err = rel_l2(g, gref)
+    print(f"NN Gram grad bf16={bf16} kind={kind}: loss {loss.value:.6g} vs {lref:.6g}; grad rel L2 {err:.3g}, "
+          f"cosine {_cos(g, gref):.6f}")
+    if bf16:
+        assert abs(loss.value - lref) <= 5e-2 * lref
+        assert err <= 5e-2 and _cos(g, gref) >= 0.999
+    else:
+        assert abs(loss.value - lref) <= 1e-5 * lref
+        assert err <= 1e-4
+    lat.close()
+
+
+def test_save_load_keeps_the_form(tmp_path):
+    lat, fat, naik = make_lattice(DIMS, 327)
+    lib = hisq.library()
+    _init(lat, False)
+    _set(lat, _theta(328))
+    assert lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM) == 0
+    r = torch.from_numpy(synth.sources(DIMS, 2, 329)).to(DEV)
+    z1 = _apply(lat, r)
+    path = str(tmp_path / "gram.bin").encode()
+    hisq._check(lat.ctx, lib.hisq_nn_save(lat.ctx, path))
+    hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, L, 8, 99))
+    assert lib.hisq_nn_set_precision(lat.ctx, 0) == 0
+    hisq._check(lat.ctx, lib.hisq_nn_load(lat.ctx, path))
+    z2 = _apply(lat, r)
+    assert np.array_equal(z1, z2)
+    assert lib.hisq_nn_set_form(lat.ctx, 2) == hisq.HISQ_ERR_ARG
     lat.close()

@@ -92,13 +92,25 @@ def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup
     return t0.elapsed_time(t1) / steps, float(np.mean(per_launch))
 
 
+# per-study settings: rhs of the FCG solve, training sources x snapshots (every `snap` plain-CG
+# iterations, harvest tolerance), epochs, and whether the plain FP64 solve runs
+STUDY = {
+    "c3": dict(n_fcg=None, nsrc=16, nsnap=16, snap=60, harvest_tol=1e-8, epochs=20, plain=True),
+    # 64^3 x 16: the network and its training scale with 16 x the vector volume, so the learned
+    # solve runs on 4 of the 32 rhs with 64 training pairs; the plain FP64 solve is left out
+    "c4": dict(n_fcg=4, nsrc=8, nsnap=8, snap=100, harvest_tol=1e-6, epochs=5, plain=False),
+}
+
+
 def solver_study(args, torch, synth, hisq, pm):
     """48^3x12 (16 Z2 rhs, m = 0.01) or 64^3x16 (32 Gaussian rhs, m = 0.005): CG seconds per rhs
-    to a true FP64 residual 1e-8 for plain FP64, mixed precision (FP16 links) and the flexible CG
-    with the learned preconditioner (trained here on 256 pairs harvested from plain CG on the same
-    links), with iterations, peak device memory and the Dslash GB/s inside the mixed solve."""
+    to a true FP64 residual 1e-8 for mixed precision (FP16 links), plain FP64 (48^3x12) and the
+    flexible CG with the learned preconditioner (trained here on pairs harvested from plain CG on
+    the same links), with iterations, peak device memory, the Dslash Gflop/s inside each solve
+    and the cost of one network application."""
     import ctypes
     name = args.workload
+    st = STUDY[name]
     cfg = synth.WORKLOADS[name]
     dims, n, mass, tol = cfg["dims"], cfg["n"], cfg["mass"], cfg["tol"]
     seed = synth.workload_seed(name)
@@ -113,18 +125,20 @@ def solver_study(args, torch, synth, hisq, pm):
     out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, {n} {cfg['source']} rhs, tol {tol}",
            "link_generation_s": round(t_gen, 1)}
     lib = hisq.library()
+    epochs = args.epochs if args.epochs else st["epochs"]
 
     def progress(msg):
         print(f"[{name}] {msg}", file=sys.stderr, flush=True)
 
-    def solve(label, **kw):
+    def solve(label, rhs, **kw):
         progress(f"solve {label}")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        x, info = lat.cg(mass, b, tol=tol, max_iter=60000, **kw)
+        x, info = lat.cg(mass, rhs, tol=tol, max_iter=60000, **kw)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t
-        out[label] = {"s_per_rhs": round(sec / n, 5), "seconds": round(sec, 3),
+        nr = rhs.shape[0]
+        out[label] = {"n_rhs": nr, "s_per_rhs": round(sec / nr, 5), "seconds": round(sec, 3),
                       "iters_mean": round(float(np.mean(info["iters"])), 1),
                       "iters_max": max(info["iters"]), "true_resid_max": max(info["true_resid"]),
                       "converged": sum(info["converged"]), "fell_back": sum(info["fell_back"]),
@@ -133,10 +147,11 @@ def solver_study(args, torch, synth, hisq, pm):
                       "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
         return x, info
 
-    solve("mixed_f16links", kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
-    solve("plain_f64", kind=hisq.HISQ_CG_F64)
-    # training pairs along plain-CG trajectories of 16 Gaussian sources: 16 snapshots each
-    nsrc, nsnap = 16, 16
+    solve("mixed_f16links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
+    if st["plain"]:
+        solve("plain_f64", b, kind=hisq.HISQ_CG_F64)
+    # training pairs along plain-CG trajectories of Gaussian sources
+    nsrc, nsnap = st["nsrc"], st["nsnap"]
     bs = torch.from_numpy(synth.sources(dims, nsrc, seed + 2)).to(dev)
     r = torch.empty((nsnap * nsrc, 3, lat.vh), dtype=torch.complex128, device=dev)
     y = torch.empty_like(r)
@@ -144,40 +159,48 @@ def solver_study(args, torch, synth, hisq, pm):
     progress("harvest training pairs")
     torch.cuda.synchronize()
     t = time.perf_counter()
-    hisq._check(lat.ctx, lib.hisq_nn_harvest(lat.ctx, mass, nsrc, hisq._ptr(bs), 1e-8, nsnap,
-                                             60, hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
-    out["harvest"] = {"pairs": npairs.value, "seconds": round(time.perf_counter() - t, 2)}
+    hisq._check(lat.ctx, lib.hisq_nn_harvest(lat.ctx, mass, nsrc, hisq._ptr(bs), st["harvest_tol"], nsnap,
+                                             st["snap"], hisq._ptr(r), hisq._ptr(y), ctypes.byref(npairs)))
+    out["harvest"] = {"pairs": npairs.value, "sources": nsrc, "snapshot_every": st["snap"],
+                      "seconds": round(time.perf_counter() - t, 2)}
+    del bs
     # Gram form N^dag N (Hermitian positive semi-definite) trained on the residual-norm loss
     hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, 4, 8, seed))
     hisq._check(lat.ctx, lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM))
     hisq._check(lat.ctx, lib.hisq_nn_set_loss(lat.ctx, hisq.HISQ_NN_LOSS_RESIDUAL, mass))
-    hist = (ctypes.c_double * args.epochs)()
+    hist = (ctypes.c_double * epochs)()
     batch, lr = 16, 1e-2
     progress("train the network")
     t = time.perf_counter()
     hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
-                                           args.epochs, batch, lr, seed, hist))
-    out["training"] = {"form": "gram", "loss": "residual", "epochs": args.epochs, "batch": batch,
+                                           epochs, batch, lr, seed, hist))
+    out["training"] = {"form": "gram", "loss": "residual", "epochs": epochs, "batch": batch,
                        "lr": lr, "bf16": True, "seconds": round(time.perf_counter() - t, 2),
-                       "loss_first": round(hist[0], 5), "loss_last": round(hist[args.epochs - 1], 5)}
+                       "loss_first": round(hist[0], 5), "loss_last": round(hist[epochs - 1], 5)}
     del r, y
-    # one preconditioner application on the n-rhs bundle (FP32 vectors), as inside the FCG
-    rv = b.to(torch.complex64)
+    bf = b if st["n_fcg"] is None else b[:st["n_fcg"]].contiguous()
+    nf = bf.shape[0]
+    # one preconditioner application on the FCG bundle (FP32 vectors), as inside the FCG
+    rv = bf.to(torch.complex64)
     zv = torch.empty_like(rv)
     for _ in range(2):
-        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, n, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
+        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, nf, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
     e0, e1 = _events(torch)
     e0.record()
     for _ in range(5):
-        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, n, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
+        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, nf, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
     e1.record()
     torch.cuda.synchronize()
-    out["network_apply_ms"] = round(e0.elapsed_time(e1) / 5, 3)
+    out["network_apply_ms"] = {"n_rhs": nf, "ms": round(e0.elapsed_time(e1) / 5, 3)}
     del rv, zv
-    solve("fcg_learned_f16links", kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F16)
-    out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out["mixed_f16links"]["seconds"], 3)
-    out["speedup_fcg_vs_mixed"] = round(out["mixed_f16links"]["seconds"] / out["fcg_learned_f16links"]["seconds"], 3)
-    out["iteration_ratio_fcg_vs_mixed"] = round(out["fcg_learned_f16links"]["iters_mean"] / out["mixed_f16links"]["iters_mean"], 3)
+    if nf != n:  # the mixed solver on the same bundle, for the iteration and time comparison
+        solve("mixed_f16links_fcg_bundle", bf, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
+    solve("fcg_learned_f16links", bf, kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F16)
+    ref = out["mixed_f16links" if nf == n else "mixed_f16links_fcg_bundle"]
+    if st["plain"]:
+        out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out["mixed_f16links"]["seconds"], 3)
+    out["speedup_fcg_vs_mixed"] = round(ref["seconds"] / out["fcg_learned_f16links"]["seconds"], 3)
+    out["iteration_ratio_fcg_vs_mixed"] = round(out["fcg_learned_f16links"]["iters_mean"] / ref["iters_mean"], 3)
     lat.close()
     return out
 
@@ -194,7 +217,8 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
                     help="c1: Dslash throughput at 32^3x8 (default, the timed steps); c3/c4: the "
                          "solver comparison at 48^3x12 / 64^3x16 (plain FP64, mixed, learned FCG)")
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=0,
+                    help="training epochs of the solver study (0: 20 at 48^3x12, 5 at 64^3x16)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), then --steps FP32 Dslash steps")

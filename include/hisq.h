@@ -129,7 +129,11 @@ typedef struct {
   int lds_links;         /* 1, 2, 3: a workgroup of 64 sites x 4, 8, 16 waves stages its sites'  */
                          /*    links in LDS and its waves loop over the rhs tiles (requires      */
                          /*    sites_per_block = 64, rhs_per_thread <= 4 (<= 2 for 16 waves) and */
-                         /*    LDS for 64 sites' links: not FP64)                                */
+                         /*    LDS for 64 sites' links: not FP64);                               */
+                         /* 4, 5, 6: the same with the links staged one direction at a time in  */
+                         /*    two LDS buffers, the next direction loading while the current one */
+                         /*    is applied; 16 waves x 1 rhs tile (4), 16 x 2 (5), 8 x 2 (6), so  */
+                         /*    n <= 16, 32, 16 rhs tiles; rhs_per_thread <= 2; not FP64          */
   int xcd_map;           /* LDS form only: 0 = each XCD takes a contiguous range of sites; 1 =    */
                          /*    each XCD takes Lz/8 z slices for all t (needs (Lx/2)*Ly % 64 == 0 */
                          /*    and Lz % 8 == 0); 2 = each XCD takes 1/8 of the 64-site blocks of */

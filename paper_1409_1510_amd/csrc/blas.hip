@@ -111,41 +111,6 @@ __global__ void k_reduce_alpha(const double *__restrict__ partial, int nblk, CGS
   }
 }
 
-// x += alpha p; r -= alpha q; partials of ||r||^2.
-template <typename C, typename CX>
-__global__ void __launch_bounds__(kThreads)
-k_update_xr(CX *__restrict__ x, C *__restrict__ rv, const C *__restrict__ p, const C *__restrict__ q,
-            unsigned len, int nblk, const CGState *S, double *__restrict__ partial) {
-  __shared__ double red[4];
-  const int r = blockIdx.y;
-  if (!S->active[r]) return;
-  using R = decltype(C{}.x);
-  using RX = decltype(CX{}.x);
-  const R a = R(S->alpha[r]);
-  const RX ax = RX(S->alpha[r]);
-  const size_t off = size_t(r) * len;
-  double rr = 0.0;
-  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    unsigned j = base + k * kThreads;
-    if (j < len) {
-      C pj = p[off + j], qj = q[off + j], rj = rv[off + j];
-      CX xj = x[off + j];
-      xj.x = fma(ax, RX(pj.x), xj.x);
-      xj.y = fma(ax, RX(pj.y), xj.y);
-      rj.x = fma(-a, qj.x, rj.x);
-      rj.y = fma(-a, qj.y, rj.y);
-      x[off + j] = xj;
-      rv[off + j] = rj;
-      rr = fma(double(rj.x), double(rj.x), rr);
-      rr = fma(double(rj.y), double(rj.y), rr);
-    }
-  }
-  rr = block_sum(rr, red);
-  if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = rr;
-}
-
 __global__ void k_reduce_beta(const double *__restrict__ partial, int nblk, CGState *S, double tol2) {
   __shared__ double red[4];
   const int r = blockIdx.x;
@@ -168,14 +133,46 @@ __global__ void k_reduce_beta(const double *__restrict__ partial, int nblk, CGSt
   }
 }
 
-// p = r + beta p
+// r -= alpha q and the partials of ||r||^2 (the solution update is left to k_update_px)
 template <typename C>
 __global__ void __launch_bounds__(kThreads)
-k_update_p(const C *__restrict__ rv, C *__restrict__ p, unsigned len, const CGState *S) {
+k_update_r(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, const CGState *S,
+           double *__restrict__ partial) {
+  __shared__ double red[4];
   const int r = blockIdx.y;
   if (!S->active[r]) return;
   using R = decltype(C{}.x);
+  const R a = R(S->alpha[r]);
+  const size_t off = size_t(r) * len;
+  double rr = 0.0;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C qj = q[off + j], rj = rv[off + j];
+      rj.x = fma(-a, qj.x, rj.x);
+      rj.y = fma(-a, qj.y, rj.y);
+      rv[off + j] = rj;
+      rr = fma(double(rj.x), double(rj.x), rr);
+      rr = fma(double(rj.y), double(rj.y), rr);
+    }
+  }
+  rr = block_sum(rr, red);
+  if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = rr;
+}
+
+// x += alpha p; p = r + beta p: the solution update of the step, deferred to the pass that
+// rewrites p anyway (one read of p instead of two)
+template <typename C, typename CX>
+__global__ void __launch_bounds__(kThreads)
+k_update_px(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p, unsigned len, const CGState *S) {
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  using R = decltype(C{}.x);
+  using RX = decltype(CX{}.x);
   const R b = R(S->beta[r]);
+  const RX ax = RX(S->alpha[r]);
   const size_t off = size_t(r) * len;
   const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
 #pragma unroll
@@ -183,6 +180,10 @@ k_update_p(const C *__restrict__ rv, C *__restrict__ p, unsigned len, const CGSt
     unsigned j = base + k * kThreads;
     if (j < len) {
       C pj = p[off + j], rj = rv[off + j];
+      CX xj = x[off + j];
+      xj.x = fma(ax, RX(pj.x), xj.x);
+      xj.y = fma(ax, RX(pj.y), xj.y);
+      x[off + j] = xj;
       pj.x = fma(b, pj.x, rj.x);
       pj.y = fma(b, pj.y, rj.y);
       p[off + j] = pj;
@@ -514,43 +515,39 @@ int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, 
   return HISQ_OK;
 }
 
-int cg_update_xr(hisq_ctx *ctx, int body_prec, bool x64, void *x, void *r, const void *p,
-                 const void *q, CGState *S, int n, double *partial) {
+int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n, double *partial) {
   const unsigned len = 3u * ctx->g.vh;
   const int nblk = blas_nblk(ctx);
   dim3 grid(nblk, n);
   if (body_prec == HISQ_F64)
-    k_update_xr<double2, double2><<<grid, kThreads, 0, ctx->stream>>>(
-        static_cast<double2 *>(x), static_cast<double2 *>(r), static_cast<const double2 *>(p),
-        static_cast<const double2 *>(q), len, nblk, S, partial);
-  else if (x64)
-    k_update_xr<float2, double2><<<grid, kThreads, 0, ctx->stream>>>(
-        static_cast<double2 *>(x), static_cast<float2 *>(r), static_cast<const float2 *>(p),
-        static_cast<const float2 *>(q), len, nblk, S, partial);
+    k_update_r<double2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<double2 *>(r), static_cast<const double2 *>(q),
+                                                            len, nblk, S, partial);
   else
-    k_update_xr<float2, float2><<<grid, kThreads, 0, ctx->stream>>>(
-        static_cast<float2 *>(x), static_cast<float2 *>(r), static_cast<const float2 *>(p),
-        static_cast<const float2 *>(q), len, nblk, S, partial);
-  LAUNCHCHK(ctx, "k_update_xr");
+    k_update_r<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<float2 *>(r), static_cast<const float2 *>(q),
+                                                           len, nblk, S, partial);
+  LAUNCHCHK(ctx, "k_update_r");
+  return HISQ_OK;
+}
+
+int cg_update_px(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, const CGState *S, int n) {
+  const unsigned len = 3u * ctx->g.vh;
+  dim3 grid(blas_nblk(ctx), n);
+  if (body_prec == HISQ_F64)
+    k_update_px<double2, double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(x), static_cast<const double2 *>(r), static_cast<double2 *>(p), len, S);
+  else if (x64)
+    k_update_px<float2, double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S);
+  else
+    k_update_px<float2, float2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<float2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S);
+  LAUNCHCHK(ctx, "k_update_px");
   return HISQ_OK;
 }
 
 int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2) {
   k_reduce_beta<<<n, kThreads, 0, ctx->stream>>>(partial, blas_nblk(ctx), S, tol2);
   LAUNCHCHK(ctx, "k_reduce_beta");
-  return HISQ_OK;
-}
-
-int cg_update_p(hisq_ctx *ctx, int body_prec, const void *r, void *p, const CGState *S, int n) {
-  const unsigned len = 3u * ctx->g.vh;
-  dim3 grid(blas_nblk(ctx), n);
-  if (body_prec == HISQ_F64)
-    k_update_p<double2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<const double2 *>(r),
-                                                            static_cast<double2 *>(p), len, S);
-  else
-    k_update_p<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<const float2 *>(r),
-                                                           static_cast<float2 *>(p), len, S);
-  LAUNCHCHK(ctx, "k_update_p");
   return HISQ_OK;
 }
 

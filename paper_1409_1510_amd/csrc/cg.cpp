@@ -178,9 +178,9 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
     int nblk_d = 0;
     RETCHK(cg_apply_op(ctx, op_prec, mass, n, v.p, v.t, v.q, partial, &nblk_d, S->active));
     RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, n));
-    RETCHK(cg_update_xr(ctx, body, !mixed, mixed ? v.xh : x, v.r, v.p, v.q, S, n, partial));
+    RETCHK(cg_update_r(ctx, body, v.r, v.q, S, n, partial));
     RETCHK(cg_reduce_beta(ctx, partial, S, n, tol2));
-    RETCHK(cg_update_p(ctx, body, v.r, v.p, S, n));
+    RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : x, v.r, v.p, S, n));
     ++it;
     RETCHK(snapshot());
     if (mixed && it % reliable_every == 0) {

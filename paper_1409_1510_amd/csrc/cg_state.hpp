@@ -29,10 +29,9 @@ struct CGState {
 struct hisq_ctx;
 int blas_nblk(const hisq_ctx *ctx);
 int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n);
-int cg_update_xr(hisq_ctx *ctx, int body_prec, bool x64, void *x, void *r, const void *p,
-                 const void *q, CGState *S, int n, double *partial);
 int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
-int cg_update_p(hisq_ctx *ctx, int body_prec, const void *r, void *p, const CGState *S, int n);
+int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n, double *partial);
+int cg_update_px(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, const CGState *S, int n);
 int cg_select(hisq_ctx *ctx, CGState *S, int n, int all);
 int cg_accum_x(hisq_ctx *ctx, void *x64, void *xh32, const int *mask, int n);
 int cg_replace_r(hisq_ctx *ctx, int body_prec, const void *b, const void *mx, void *r, void *p,

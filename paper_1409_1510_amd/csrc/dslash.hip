@@ -27,7 +27,10 @@ DslashFn lookup(int prec, int recon, bool epi, const hisq_launch &c) {
 size_t lds_bytes(int prec, int recon, const hisq_launch &c) {
   if (!c.lds_links) return 0;
   const size_t elem = prec == HISQ_F64 ? 16 : (prec == HISQ_F32 ? 8 : 4);
-  const size_t row2 = (prec != HISQ_F64 && recon == 14) ? size_t(24) * 64 * (prec == HISQ_F64 ? 16 : 8) : 0;
+  const bool r14 = prec != HISQ_F64 && recon == 14;
+  if (c.lds_links >= 4)  // two buffers of one direction's planes (+ rebuilt Naik rows)
+    return 2 * size_t(r14 ? 32 : 36) * 64 * elem + (r14 ? size_t(12) * 64 * 8 : 0);
+  const size_t row2 = r14 ? size_t(24) * 64 * 8 : 0;
   return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem + row2;
 }
 
@@ -37,9 +40,21 @@ bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size
   if (rt != 1 && rt != 2 && rt != 4 && rt != 8 && rt != 16) return false;
   if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
-  if (c.lds_links < 0 || c.lds_links > 3) return false;
+  if (c.lds_links < 0 || c.lds_links > 6) return false;
   if (c.xcd_map < 0 || c.xcd_map > 2 || (c.xcd_map != 0 && !c.lds_links)) return false;
   return lookup(prec, 18, epi, c) != nullptr && lookup(prec, 14, epi, c) != nullptr;
+}
+
+// rhs tiles a workgroup of the direction-pipelined forms can hold (their waves keep every tile's
+// accumulators across the four directions)
+int max_tiles(const hisq_launch &c) {
+  if (c.lds_links == 4) return 16;
+  if (c.lds_links == 5) return 32;
+  if (c.lds_links == 6) return 16;
+  return 1 << 30;
+}
+bool fits_n(const hisq_launch &c, int n) {
+  return (n + c.rhs_per_thread - 1) / c.rhs_per_thread <= max_tiles(c);
 }
 
 int next_pow2(int n) {
@@ -103,6 +118,8 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
     return set_err(ctx, HISQ_ERR_ARG, "Dslash launch configuration needs %zu bytes of LDS (%zu available)",
                    lds_bytes(prec, l.recon, c), ctx->lds_max);
   const Geo geo = geometry(ctx->g, n, c);
+  if (!fits_n(c, n))
+    return set_err(ctx, HISQ_ERR_ARG, "this Dslash form holds at most %d rhs tiles (n = %d)", max_tiles(c), n);
   if (c.xcd_map && geo.xmap != c.xcd_map) return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
          mass2, pvec, partial, active, geo.xmap, geo.zmap_bps, geo.zmap_zr};
@@ -161,11 +178,11 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
     if (rt > next_pow2(n)) break;
     for (int spb : {256, 64})
       for (int nt : {0, 1})
-        for (int lds : {0, 1, 2, 3})
+        for (int lds = 0; lds <= 6; ++lds)
           for (int xm : {0, 1, 2}) {
             hisq_launch c{rt, spb, nt, lds, xm};
             if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
-            if (!map_possible(g, xm)) continue;
+            if (!map_possible(g, xm) || !fits_n(c, n)) continue;
             float ms;
             rc = time_cfg(c, 3, &ms);
             if (rc != HISQ_OK) break;
@@ -250,6 +267,9 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
         return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: invalid configuration (rt %d, spb %d, nt %d)",
                        cfg->rhs_per_thread, cfg->sites_per_block, cfg->nontemporal_links);
     }
+    if (!fits_n(c, n))
+      return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: this form holds at most %d rhs tiles (n = %d)",
+                     max_tiles(c), n);
     t.cfg = c;
     t.state = TuneEntry::FORCED;
   }
@@ -325,7 +345,7 @@ extern "C" int hisq_load_tuning(hisq_ctx *ctx, const char *path, int *n_loaded) 
     if (prec < 0 || prec > 2 || n < 1 || n > HISQ_MAX_RHS || (e != 0 && e != 1)) continue;
     if (!ctx->links[prec].base || ctx->links[prec].recon != recon) continue;
     if (!config_valid(prec, e != 0, c, recon, ctx->lds_max)) continue;
-    if (!map_possible(g, c.xcd_map)) continue;
+    if (!map_possible(g, c.xcd_map) || !fits_n(c, n)) continue;
     TuneEntry &t = ctx->tune[prec][n][e];
     t.cfg = c;
     t.state = TuneEntry::TUNED;

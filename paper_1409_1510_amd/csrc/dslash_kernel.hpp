@@ -275,6 +275,39 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
   }
 }
 
+// Site block of an LDS-form workgroup under the XCD map of the launch (false: none).
+__device__ inline bool lds_block(const Args &a, int &sblk) {
+  const Geometry &g = a.g;
+  if (a.xmap == 2) {
+    // XCD k owns the blocks [k, k+1) * bps/8 of every (z, t) plane (with Lx = 32: four y rows)
+    // and walks the planes z-major.  The sites in flight on an XCD then span a few z slices of a
+    // thin slab whose t extent is the whole lattice, so the t and z neighbours they gather (the
+    // Naik hops reach 3 slices away) are mostly still in that XCD's L2.
+    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int bpx = a.zmap_bps >> 3;
+    const int zt = j / bpx;  // z * Lt + t
+    const int z = zt / g.lt, t = zt - z * g.lt;
+    if (z >= g.lz) return false;
+    sblk = (t * g.lz + z) * a.zmap_bps + k * bpx + (j - zt * bpx);
+  } else if (a.xmap == 1) {
+    // XCD k owns the z slices [k Lz/8, (k+1) Lz/8) for every t: the z and t neighbours of its
+    // sites stay mostly in its own L2 (with contiguous chunks, Lt = 8 would give each XCD a single
+    // t slice and send every t hop to another XCD's data)
+    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int per_t = a.zmap_zr * a.zmap_bps;
+    const int t = j / per_t;
+    if (t >= g.lt) return false;
+    const int rem = j - t * per_t;
+    const int zl = rem / a.zmap_bps;
+    sblk = (t * g.lz + k * a.zmap_zr + zl) * a.zmap_bps + (rem - zl * a.zmap_bps);
+  } else {
+    const int chunk = gridDim.x >> 3;
+    sblk = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    if (sblk >= a.nsblk) return false;
+  }
+  return true;
+}
+
 // Naik link k (0..7: hops 8 + k) of lane `lane` from the staged LDS copy: rows 0 and 1 from the
 // stored planes and, for 14-real links, row 2 from the planes rebuilt once per site.
 template <typename Real, typename LT, bool R14>
@@ -315,33 +348,7 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
   LT *sl = reinterpret_cast<LT *>(smem_raw);
   const Geometry &g = a.g;
   int sblk;
-  if (a.xmap == 2) {
-    // XCD k owns the blocks [k, k+1) * bps/8 of every (z, t) plane (with Lx = 32: four y rows)
-    // and walks the planes z-major.  The sites in flight on an XCD then span a few z slices of a
-    // thin slab whose t extent is the whole lattice, so the t and z neighbours they gather (the
-    // Naik hops reach 3 slices away) are mostly still in that XCD's L2.
-    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int bpx = a.zmap_bps >> 3;
-    const int zt = j / bpx;  // z * Lt + t
-    const int z = zt / g.lt, t = zt - z * g.lt;
-    if (z >= g.lz) return;  // uniform for the whole workgroup
-    sblk = (t * g.lz + z) * a.zmap_bps + k * bpx + (j - zt * bpx);
-  } else if (a.xmap == 1) {
-    // XCD k owns the z slices [k Lz/8, (k+1) Lz/8) for every t: the z and t neighbours of its
-    // sites stay mostly in its own L2 (with contiguous chunks, Lt = 8 would give each XCD a single
-    // t slice and send every t hop to another XCD's data)
-    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
-    const int per_t = a.zmap_zr * a.zmap_bps;
-    const int t = j / per_t;
-    if (t >= g.lt) return;  // uniform for the whole workgroup
-    const int rem = j - t * per_t;
-    const int zl = rem / a.zmap_bps;
-    sblk = (t * g.lz + k * a.zmap_zr + zl) * a.zmap_bps + (rem - zl * a.zmap_bps);
-  } else {
-    const int chunk = gridDim.x >> 3;
-    sblk = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
-    if (sblk >= a.nsblk) return;  // uniform for the whole workgroup
-  }
+  if (!lds_block(a, sblk)) return;  // uniform for the whole workgroup
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned vh = g.vh;
   const unsigned s = sblk * 64 + lane;
@@ -489,6 +496,256 @@ __global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
   }
 }
 
+// Write one rhs tile of an LDS-form workgroup: w = acc, or for the fused M form
+// q = m2 p - acc with the per-64-site FP64 partials of Re<p, q> (all 64 lanes of the wave take
+// part in the reduction; the partial of block sblk is written by lane 0).
+template <typename Real, int RT, bool EPI>
+__device__ inline void store_tile(const Args &a, int r0, unsigned s, int lane, int sblk, const bool (&act)[RT],
+                                  const Real (&acc_re)[RT][3], const Real (&acc_im)[RT][3]) {
+  using C = typename CT<Real>::T;
+  const unsigned vh = a.g.vh;
+  const size_t tile_off = size_t(r0) * 3 * vh;
+  C *__restrict__ out = static_cast<C *>(a.out) + tile_off;
+  if constexpr (!EPI) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      if (!act[r]) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C o;
+        o.x = acc_re[r][c];
+        o.y = acc_im[r][c];
+        out[(unsigned)(r * 3 + c) * vh + s] = o;
+      }
+    }
+  } else {
+    const C *__restrict__ pv = static_cast<const C *>(a.pvec) + tile_off;
+    const Real m2 = Real(a.mass2);
+    double dot[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      dot[r] = 0.0;
+      if (!act[r]) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const C p = pv[(unsigned)(r * 3 + c) * vh + s];
+        C o;
+        o.x = fmaR(m2, p.x, -acc_re[r][c]);
+        o.y = fmaR(m2, p.y, -acc_im[r][c]);
+        out[(unsigned)(r * 3 + c) * vh + s] = o;
+        dot[r] = fma(double(p.x), double(o.x), dot[r]);
+        dot[r] = fma(double(p.y), double(o.y), dot[r]);
+      }
+    }
+    if (a.partial) {
+      const unsigned nw = (vh + 63) / 64;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        double v = dot[r];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0 && r0 + r < a.n) a.partial[size_t(r0 + r) * nw + sblk] = v;
+      }
+    }
+  }
+}
+
+// raw link-entry load (optionally non-temporal) for LDS staging
+template <bool NT> __device__ inline float2 ld_raw(const float2 *p) {
+  if constexpr (NT) {
+    const unsigned long long u = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p));
+    return *reinterpret_cast<const float2 *>(&u);
+  } else {
+    return *p;
+  }
+}
+template <bool NT> __device__ inline __half2 ld_raw(const __half2 *p) {
+  if constexpr (NT) {
+    const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(p));
+    return *reinterpret_cast<const __half2 *>(&u);
+  } else {
+    return *p;
+  }
+}
+
+// Direction-pipelined LDS form: the workgroup (64 sites x WPB waves) stages the links of one
+// direction mu at a time -- X(x,mu), X(x-mu,mu)^dag, N(x,mu), N(x-3mu,mu)^dag -- in one of two
+// LDS buffers.  While the waves apply direction mu to their rhs tiles, the links of mu+1 are
+// already being loaded into registers, so link streaming overlaps the neighbour gathers and
+// the FMAs, and a workgroup needs a quarter of the LDS of the whole-site form.  Each wave keeps
+// the accumulators of TPW rhs tiles across the four directions (ntiles <= TPW * WPB).  Same hop
+// order and FMA sequence per rhs as k_dslash, same per-64-site partials.
+// (16 waves x 1 tile: at most 64 VGPRs, so that two workgroups share a CU)
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, int TPW, bool NT>
+__global__ void __launch_bounds__(64 * WPB, (WPB == 16 && TPW == 1) ? 8 : 1) k_dslash_mu(Args a) {
+  using C = typename CT<Real>::T;
+  constexpr int recon = R14 ? 14 : 18;
+  constexpr int NS = R14 ? 7 : 9;            // stored planes of a Naik hop
+  constexpr int PM = 18 + 2 * NS;            // stored planes of one direction
+  constexpr int NPF = (PM + WPB - 1) / WPB;  // planes each wave stages
+  constexpr int BUF = PM * 64;               // link entries per buffer
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LT *sl = reinterpret_cast<LT *>(smem_raw);          // two buffers of BUF entries
+  C *row2 = reinterpret_cast<C *>(sl + 2 * BUF);      // 14-real Naik: two buffers of 2 x 3 x 64
+  int sblk;
+  if (!lds_block(a, sblk)) return;  // uniform for the whole workgroup
+  const Geometry &g = a.g;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned vh = g.vh;
+  const unsigned s = sblk * 64 + lane;
+  const bool valid = s < vh;
+  const LT *__restrict__ links = static_cast<const LT *>(a.links);
+
+  LT pre[NPF];
+  // issue the loads of direction mu's planes (local plane p -> stored plane)
+  auto fetch = [&](int mu) {
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int p = wave + i * WPB;
+      if (p < PM && valid) {
+        int gp;
+        if (p < 9) gp = link_plane(mu, recon) + p;
+        else if (p < 18) gp = link_plane(4 + mu, recon) + p - 9;
+        else if (p < 18 + NS) gp = link_plane(8 + mu, recon) + p - 18;
+        else gp = link_plane(12 + mu, recon) + p - 18 - NS;
+        pre[i] = ld_raw<NT>(links + size_t(gp) * vh + s);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int p = wave + i * WPB;
+      if (p < PM && valid) sl[buf * BUF + p * 64 + lane] = pre[i];
+    }
+  };
+  // 14-real Naik: row 2 of the two Naik hops of the buffer, once per site
+  auto rebuild = [&](int buf) {
+    if constexpr (R14) {
+      for (int item = threadIdx.x; item < 2 * 64; item += 64 * WPB) {
+        const int k = item >> 6, ln = item & 63;
+        Lnk<Real> Lk;
+        load_link<Real, LT, true, false>(sl + buf * BUF, 18 + k * NS, 64u, ln, Lk);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          C v;
+          v.x = Lk.re[2][b];
+          v.y = Lk.im[2][b];
+          row2[(buf * 6 + k * 3 + b) * 64 + ln] = v;
+        }
+      }
+      __syncthreads();
+    }
+  };
+
+  int x = 0, y = 0, z = 0, t = 0;
+  if (valid) {
+    const int xh = s % g.lxh;
+    int rest = s / g.lxh;
+    y = rest % g.ly;
+    rest /= g.ly;
+    z = rest % g.lz;
+    t = rest / g.lz;
+    x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+  }
+  const unsigned rowbase = s - (x >> 1);
+
+  bool act[TPW][RT];
+  Real acc_re[TPW][RT][3], acc_im[TPW][RT][3];
+#pragma unroll
+  for (int tw = 0; tw < TPW; ++tw) {
+    const int r0 = (wave + tw * WPB) * RT;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      act[tw][r] = valid && (wave + tw * WPB < a.ntiles) && (r0 + r < a.n) && (!a.active || a.active[r0 + r]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc_re[tw][r][c] = acc_im[tw][r][c] = Real(0);
+    }
+  }
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  rebuild(0);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const int buf = mu & 1;
+    if (mu < 3) fetch(mu + 1);
+    if (valid) {
+      unsigned f1, b1, f3, b3;
+      if (mu == 0) {
+        const int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
+        const int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
+        const int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
+        const int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
+        f1 = rowbase + (xf1 >> 1);
+        b1 = rowbase + (xb1 >> 1);
+        f3 = rowbase + (xf3 >> 1);
+        b3 = rowbase + (xb3 >> 1);
+      } else {
+        const int c = mu == 1 ? y : (mu == 2 ? z : t);
+        const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+        const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+        f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
+        b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
+        f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
+        b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
+      }
+      const LT *bl = sl + buf * BUF;
+#pragma unroll
+      for (int tw = 0; tw < TPW; ++tw) {
+        if (wave + tw * WPB >= a.ntiles) continue;
+        const C *__restrict__ in = static_cast<const C *>(a.in) + size_t((wave + tw * WPB) * RT) * 3 * vh;
+        Lnk<Real> Lk;
+        load_link<Real, LT, false, false>(bl, 0, 64u, lane, Lk);
+        apply_hop<Real, RT, false>(Lk, in, vh, f1, act[tw], acc_re[tw], acc_im[tw]);
+        load_link<Real, LT, false, false>(bl, 9, 64u, lane, Lk);
+        apply_hop<Real, RT, true>(Lk, in, vh, b1, act[tw], acc_re[tw], acc_im[tw]);
+        if constexpr (!R14) {
+          load_link<Real, LT, false, false>(bl, 18, 64u, lane, Lk);
+        } else {
+#pragma unroll
+          for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < 3; ++cb) ld_link<false>(bl + (18 + ra * 3 + cb) * 64 + lane, Lk.re[ra][cb], Lk.im[ra][cb]);
+#pragma unroll
+          for (int cb = 0; cb < 3; ++cb) {
+            const C v = row2[(buf * 6 + cb) * 64 + lane];
+            Lk.re[2][cb] = v.x;
+            Lk.im[2][cb] = v.y;
+          }
+        }
+        apply_hop<Real, RT, false>(Lk, in, vh, f3, act[tw], acc_re[tw], acc_im[tw]);
+        if constexpr (!R14) {
+          load_link<Real, LT, false, false>(bl, 27, 64u, lane, Lk);
+        } else {
+#pragma unroll
+          for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < 3; ++cb)
+              ld_link<false>(bl + (18 + NS + ra * 3 + cb) * 64 + lane, Lk.re[ra][cb], Lk.im[ra][cb]);
+#pragma unroll
+          for (int cb = 0; cb < 3; ++cb) {
+            const C v = row2[(buf * 6 + 3 + cb) * 64 + lane];
+            Lk.re[2][cb] = v.x;
+            Lk.im[2][cb] = v.y;
+          }
+        }
+        apply_hop<Real, RT, true>(Lk, in, vh, b3, act[tw], acc_re[tw], acc_im[tw]);
+      }
+    }
+    if (mu < 3) {
+      stash(buf ^ 1);
+      __syncthreads();
+      rebuild(buf ^ 1);
+    }
+  }
+#pragma unroll
+  for (int tw = 0; tw < TPW; ++tw)
+    if (wave + tw * WPB < a.ntiles)
+      store_tile<Real, RT, EPI>(a, (wave + tw * WPB) * RT, s, lane, sblk, act[tw], acc_re[tw], acc_im[tw]);
+}
+
 using DslashFn = void (*)(const Args &, dim3, hipStream_t);
 
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
@@ -502,6 +759,28 @@ void launch_lds(const Args &a, dim3 grid, hipStream_t st) {
   constexpr size_t lds = size_t(R14 ? 128 : 144) * 64 * sizeof(LT) +
                          (R14 ? size_t(24) * 64 * sizeof(typename CT<Real>::T) : 0);
   k_dslash_lds<Real, LT, RT, R14, EPI, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
+}
+
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, int TPW, bool NT>
+void launch_mu(const Args &a, dim3 grid, hipStream_t st) {
+  constexpr size_t lds = 2 * size_t(R14 ? 32 : 36) * 64 * sizeof(LT) +
+                         (R14 ? size_t(12) * 64 * sizeof(typename CT<Real>::T) : 0);
+  k_dslash_mu<Real, LT, RT, R14, EPI, WPB, TPW, NT><<<grid, 64 * WPB, lds, st>>>(a);
+}
+
+// direction-pipelined forms: 4 = 16 waves x 1 tile each, 5 = 16 waves x 2 tiles, 6 = 8 waves x 2
+template <typename Real, typename LT, bool R14, bool EPI, bool NT>
+DslashFn pick_mu(int rt, int lds) {
+  if (rt == 1) {
+    if (lds == 4) return launch_mu<Real, LT, 1, R14, EPI, 16, 1, NT>;
+    if (lds == 5) return launch_mu<Real, LT, 1, R14, EPI, 16, 2, NT>;
+    if (lds == 6) return launch_mu<Real, LT, 1, R14, EPI, 8, 2, NT>;
+  } else if (rt == 2) {
+    if (lds == 4) return launch_mu<Real, LT, 2, R14, EPI, 16, 1, NT>;
+    if (lds == 5) return launch_mu<Real, LT, 2, R14, EPI, 16, 2, NT>;
+    if (lds == 6) return launch_mu<Real, LT, 2, R14, EPI, 8, 2, NT>;
+  }
+  return nullptr;
 }
 
 template <typename Real, typename LT, bool R14, bool EPI, int WPB, bool NT>
@@ -520,6 +799,7 @@ DslashFn pick_lds_rt(int rt) {
 template <typename Real, typename LT, bool R14, bool EPI, bool NT>
 DslashFn pick_lds(int rt, int lds) {
   if constexpr (sizeof(LT) > 8) return nullptr;  // FP64 links do not fit LDS twice per CU
+  else if (lds >= 4) return pick_mu<Real, LT, R14, EPI, NT>(rt, lds);
   if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
   if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
   if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);

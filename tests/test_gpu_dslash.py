@@ -200,19 +200,19 @@ def test_full_size_32c8_sampled_sites():
 
 
 ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
-            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3) for xm in (0, 1, 2)
+            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3, 4, 5, 6) for xm in (0, 1, 2)
                for nt in (0, 1)])
 
 
 def _cfg_valid(prec, cfg, dims):
     """The launch rules of the header: FP64 has no 16-rhs tile and no LDS form; the 16-wave LDS
-    form takes at most 2 rhs per thread; the z-slab map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0,
-    the y-slab map (Lx/2)*Ly % 512 == 0."""
+    form and the direction-pipelined forms take at most 2 rhs per thread; the z-slab map needs
+    (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0, the y-slab map (Lx/2)*Ly % 512 == 0."""
     rt, spb, nt, lds, xm = cfg
     plane = dims[0] // 2 * dims[1]
     if prec == hisq.HISQ_F64 and (rt == 16 or lds):
         return False
-    if lds == 3 and rt > 2:
+    if lds >= 3 and rt > 2:
         return False
     if xm == 1 and not (plane % 64 == 0 and dims[2] % 8 == 0):
         return False
@@ -268,4 +268,27 @@ def test_every_launch_config_bit_identical(prec, recon, dims):
     assert best in ALL_CFGS and ms > 0
     assert hisq.hisq_get_launch(lat.ctx, prec, n, 0) == best
     assert torch.equal(lat.dslash(1, prec, v).view(rdt), first[0])
+    lat.close()
+
+
+@pytest.mark.parametrize("prec", [hisq.HISQ_F32, hisq.HISQ_F16])
+def test_direction_pipelined_tile_limit(prec):
+    """The direction-pipelined forms hold 16 (forms 4, 6) or 32 (form 5) rhs tiles per workgroup:
+    n = 40 is refused with one rhs per thread and accepted as 20 tiles of 2 by form 5, with the
+    same bits as the register-tile kernel."""
+    dims, n = (8, 6, 4, 10), 40
+    lat, fat, naik = make_lattice(dims, 125)
+    v = torch.from_numpy(_vecs(dims, n, 126)).to(DEV).to(torch.complex64)
+    hisq.hisq_set_launch(lat.ctx, prec, n, (2, 256, 0, 0, 0))
+    ref = lat.dslash(1, prec, v).view(torch.float32).clone()
+    for lds in (4, 5, 6):
+        with pytest.raises(hisq.HisqError) as e:
+            hisq.hisq_set_launch(lat.ctx, prec, n, (1, 64, 0, lds, 0))
+        assert e.value.code == hisq.HISQ_ERR_ARG
+    hisq.hisq_set_launch(lat.ctx, prec, n, (2, 64, 1, 5, 0))
+    assert torch.equal(lat.dslash(1, prec, v).view(torch.float32), ref)
+    m1, pq1 = lat.apply_m(prec, 0.1, v, with_pq=True)
+    hisq.hisq_set_launch(lat.ctx, prec, n, (2, 256, 0, 0, 0))
+    m0, pq0 = lat.apply_m(prec, 0.1, v, with_pq=True)
+    assert torch.equal(m1.view(torch.float32), m0.view(torch.float32)) and torch.equal(pq1, pq0)
     lat.close()

@@ -129,6 +129,63 @@ __device__ inline void apply_hop(const Lnk<Real> &L, const typename CT<Real>::T 
   }
 }
 
+// LDS forms: the same FMA sequence as apply_hop, but every lane computes every rhs of the tile
+// (inactive lanes and rhs read clamped, in-range addresses; only active results are stored), so
+// the hops are straight-line code the compiler can schedule across.  rr[r]: the rhs of the tile
+// to read for r.  Per-lane offsets are 32-bit: a tile spans less than 4 GB (checked at launch).
+template <typename Real, int RT, bool NEG>
+__device__ inline void apply_hop_all(const Lnk<Real> &L, const typename CT<Real>::T *__restrict__ in,
+                                     unsigned vh, unsigned nbr, const int (&rr)[RT],
+                                     Real (&acc_re)[RT][3], Real (&acc_im)[RT][3]) {
+  using C = typename CT<Real>::T;
+  const char *base = reinterpret_cast<const char *>(in);
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    C v[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      v[b] = *reinterpret_cast<const C *>(base + (unsigned(rr[r] * 3 + b) * vh + nbr) * unsigned(sizeof(C)));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const Real lr = NEG ? -L.re[a][b] : L.re[a][b];
+        const Real li = NEG ? -L.im[a][b] : L.im[a][b];
+        acc_re[r][a] = fmaR(lr, v[b].x, acc_re[r][a]);
+        acc_re[r][a] = fmaR(-li, v[b].y, acc_re[r][a]);
+        acc_im[r][a] = fmaR(lr, v[b].y, acc_im[r][a]);
+        acc_im[r][a] = fmaR(li, v[b].x, acc_im[r][a]);
+      }
+    }
+  }
+}
+
+// Neighbour indices (within the input parity) of output site s at coordinates (x, y, z, t) for
+// the four hops of direction mu: +1, -1, +3, -3.
+__device__ inline void hop_sites(const Geometry &g, int mu, unsigned s, unsigned rowbase, int x, int y, int z, int t,
+                                 unsigned &f1, unsigned &b1, unsigned &f3, unsigned &b3) {
+  if (mu == 0) {
+    const int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
+    const int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
+    const int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
+    const int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
+    f1 = rowbase + (xf1 >> 1);
+    b1 = rowbase + (xb1 >> 1);
+    f3 = rowbase + (xf3 >> 1);
+    b3 = rowbase + (xb3 >> 1);
+  } else {
+    const int c = mu == 1 ? y : (mu == 2 ? z : t);
+    const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+    const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+    f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
+    b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
+    f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
+    b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
+  }
+}
+
+// Rhs of tile r0 a wave computes: rr[r] (clamped to the last rhs), ract[r] (rhs active);
+// returns whether any rhs of the tile is active.  All values are uniform across the wave.
 struct Args {
   const void *links;
   const void *in;
@@ -147,6 +204,20 @@ struct Args {
   int zmap_bps;           //   64-site blocks per (z, t) plane
   int zmap_zr;            //   z-slab map: z slices owned by each XCD (Lz / 8)
 };
+
+template <int RT>
+__device__ inline bool tile_rhs(const Args &a, int r0, int (&rr)[RT], bool (&ract)[RT]) {
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int q = r0 + r;
+    ract[r] = q < a.n && (!a.active || a.active[q]);
+    rr[r] = q < a.n ? r : a.n - 1 - r0;
+    any = any || ract[r];
+  }
+  return any;
+}
+
 
 // SPB: sites per 256-thread workgroup (256: one tile per workgroup; 64: 4 tiles, one per wave).
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
@@ -331,171 +402,6 @@ __device__ inline void load_naik_lds(const LT *__restrict__ sl, const typename C
   }
 }
 
-// LDS-staged form: a workgroup of 64 sites x WPB waves first copies the links of its 64 sites
-// (all 16 hops) into LDS, then the waves loop over the rhs tiles (wave w takes tiles w, w+WPB,
-// ...), reading the links from LDS for every tile.  Only WPB*RT rhs of a site block are in
-// flight at a time, so the neighbour vectors other workgroups gather are far more likely to be
-// found in L2 than when every thread holds all n rhs; the links still come from HBM once.
-// Same site order, hop order and FMA sequence per rhs as k_dslash (bit-identical output), and
-// the same per-64-site grouping of the fused <p, Mp> partials.
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
-__global__ void __launch_bounds__(64 * WPB) k_dslash_lds(Args a) {
-  static_assert(WPB == 4 || WPB == 8 || WPB == 16, "4, 8 or 16 waves per workgroup");
-  using C = typename CT<Real>::T;
-  constexpr int recon = R14 ? 14 : 18;
-  constexpr int PL = R14 ? 128 : 144;  // stored planes per site
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  LT *sl = reinterpret_cast<LT *>(smem_raw);
-  const Geometry &g = a.g;
-  int sblk;
-  if (!lds_block(a, sblk)) return;  // uniform for the whole workgroup
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned vh = g.vh;
-  const unsigned s = sblk * 64 + lane;
-  const bool valid = s < vh;
-  const LT *__restrict__ links = static_cast<const LT *>(a.links);
-  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access).  With
-  // NT the global loads carry the non-temporal hint, so the streamed links do not push the
-  // neighbour vectors out of L2.
-  for (int pl = wave; pl < PL; pl += WPB)
-    if (valid) {
-      if constexpr (NT) {
-        if constexpr (sizeof(LT) == 8) {
-          const unsigned long long u =
-              __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(links + size_t(pl) * vh + s));
-          *reinterpret_cast<unsigned long long *>(sl + pl * 64 + lane) = u;
-        } else {
-          const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(links + size_t(pl) * vh + s));
-          *reinterpret_cast<unsigned *>(sl + pl * 64 + lane) = u;
-        }
-      } else {
-        sl[pl * 64 + lane] = links[size_t(pl) * vh + s];
-      }
-    }
-  __syncthreads();
-  // 14-real Naik links: rebuild row 2 once per site (not once per rhs tile) into LDS planes of
-  // the arithmetic type after the stored planes, with the same arithmetic as load_link
-  C *row2 = reinterpret_cast<C *>(sl + PL * 64);
-  if constexpr (R14) {
-    for (int item = threadIdx.x; item < 8 * 64; item += 64 * WPB) {
-      const int k = item >> 6, ln = item & 63;
-      Lnk<Real> Lk;
-      load_link<Real, LT, true, false>(sl, link_plane(8 + k, recon), 64u, ln, Lk);
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        C v;
-        v.x = Lk.re[2][b];
-        v.y = Lk.im[2][b];
-        row2[(k * 3 + b) * 64 + ln] = v;
-      }
-    }
-    __syncthreads();
-  }
-
-  int x = 0, y = 0, z = 0, t = 0;
-  if (valid) {
-    const int xh = s % g.lxh;
-    int rest = s / g.lxh;
-    y = rest % g.ly;
-    rest /= g.ly;
-    z = rest % g.lz;
-    t = rest / g.lz;
-    x = 2 * xh + ((y + z + t + a.out_parity) & 1);
-  }
-  const unsigned rowbase = s - (x >> 1);
-
-  for (int tile = wave; tile < a.ntiles; tile += WPB) {
-    const int r0 = tile * RT;
-    const size_t tile_off = size_t(r0) * 3 * vh;
-    const C *__restrict__ in = static_cast<const C *>(a.in) + tile_off;
-    C *__restrict__ out = static_cast<C *>(a.out) + tile_off;
-    bool act[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) act[r] = valid && (r0 + r < a.n) && (!a.active || a.active[r0 + r]);
-    Real acc_re[RT][3], acc_im[RT][3];
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc_re[r][c] = acc_im[r][c] = Real(0);
-    // hop order as in k_dslash: per mu, fat fwd, fat bwd, Naik fwd, Naik bwd
-    if (valid) {
-#pragma unroll 1
-      for (int mu = 0; mu < 4; ++mu) {
-        unsigned f1, b1, f3, b3;
-        if (mu == 0) {
-          const int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
-          const int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
-          const int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
-          const int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
-          f1 = rowbase + (xf1 >> 1);
-          b1 = rowbase + (xb1 >> 1);
-          f3 = rowbase + (xf3 >> 1);
-          b3 = rowbase + (xb3 >> 1);
-        } else {
-          const int c = mu == 1 ? y : (mu == 2 ? z : t);
-          const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
-          const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
-          f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
-          b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
-          f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
-          b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
-        }
-        Lnk<Real> Lk;
-        load_link<Real, LT, false, false>(sl, link_plane(mu, recon), 64u, lane, Lk);
-        apply_hop<Real, RT, false>(Lk, in, vh, f1, act, acc_re, acc_im);
-        load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
-        apply_hop<Real, RT, true>(Lk, in, vh, b1, act, acc_re, acc_im);
-        load_naik_lds<Real, LT, R14>(sl, row2, mu, lane, Lk);
-        apply_hop<Real, RT, false>(Lk, in, vh, f3, act, acc_re, acc_im);
-        load_naik_lds<Real, LT, R14>(sl, row2, 4 + mu, lane, Lk);
-        apply_hop<Real, RT, true>(Lk, in, vh, b3, act, acc_re, acc_im);
-      }
-    }
-    if constexpr (!EPI) {
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        if (!act[r]) continue;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          C o;
-          o.x = acc_re[r][c];
-          o.y = acc_im[r][c];
-          out[(unsigned)(r * 3 + c) * vh + s] = o;
-        }
-      }
-    } else {
-      const C *__restrict__ pv = static_cast<const C *>(a.pvec) + tile_off;
-      const Real m2 = Real(a.mass2);
-      double dot[RT];
-#pragma unroll
-      for (int r = 0; r < RT; ++r) {
-        dot[r] = 0.0;
-        if (!act[r]) continue;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const C p = pv[(unsigned)(r * 3 + c) * vh + s];
-          C o;
-          o.x = fmaR(m2, p.x, -acc_re[r][c]);
-          o.y = fmaR(m2, p.y, -acc_im[r][c]);
-          out[(unsigned)(r * 3 + c) * vh + s] = o;
-          dot[r] = fma(double(p.x), double(o.x), dot[r]);
-          dot[r] = fma(double(p.y), double(o.y), dot[r]);
-        }
-      }
-      if (a.partial) {
-        const unsigned nw = (vh + 63) / 64;
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          double v = dot[r];
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-          if (lane == 0 && r0 + r < a.n) a.partial[size_t(r0 + r) * nw + sblk] = v;
-        }
-      }
-    }
-  }
-}
-
 // Write one rhs tile of an LDS-form workgroup: w = acc, or for the fused M form
 // q = m2 p - acc with the per-64-site FP64 partials of Re<p, q> (all 64 lanes of the wave take
 // part in the reduction; the partial of block sblk is written by lane 0).
@@ -568,6 +474,127 @@ template <bool NT> __device__ inline __half2 ld_raw(const __half2 *p) {
   }
 }
 
+// LDS-staged form: a workgroup of 64 sites x WPB waves first copies the links of its 64 sites
+// (all 16 hops) into LDS, then the waves loop over the rhs tiles (wave w takes tiles w, w+WPB,
+// ...), reading the links from LDS for every tile.  Only WPB*RT rhs of a site block are in
+// flight at a time, so the neighbour vectors other workgroups gather are far more likely to be
+// found in L2 than when every thread holds all n rhs; the links still come from HBM once.
+// Same site order, hop order and FMA sequence per rhs as k_dslash (bit-identical output), and
+// the same per-64-site grouping of the fused <p, Mp> partials.
+// (16 waves: at most 64 VGPRs, so that two workgroups share a CU)
+template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
+__global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : 1) k_dslash_lds(Args a) {
+  static_assert(WPB == 4 || WPB == 8 || WPB == 16, "4, 8 or 16 waves per workgroup");
+  using C = typename CT<Real>::T;
+  constexpr int recon = R14 ? 14 : 18;
+  constexpr int PL = R14 ? 128 : 144;  // stored planes per site
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LT *sl = reinterpret_cast<LT *>(smem_raw);
+  const Geometry &g = a.g;
+  int sblk;
+  if (!lds_block(a, sblk)) return;  // uniform for the whole workgroup
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const unsigned vh = g.vh;
+  const unsigned s = sblk * 64 + lane;
+  const bool valid = s < vh;
+  const LT *__restrict__ links = static_cast<const LT *>(a.links);
+  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access).  With
+  // NT the global loads carry the non-temporal hint, so the streamed links do not push the
+  // neighbour vectors out of L2.
+  for (int pl = wave; pl < PL; pl += WPB)
+    if (valid) {
+      if constexpr (NT) {
+        if constexpr (sizeof(LT) == 8) {
+          const unsigned long long u =
+              __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(links + size_t(pl) * vh + s));
+          *reinterpret_cast<unsigned long long *>(sl + pl * 64 + lane) = u;
+        } else {
+          const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(links + size_t(pl) * vh + s));
+          *reinterpret_cast<unsigned *>(sl + pl * 64 + lane) = u;
+        }
+      } else {
+        sl[pl * 64 + lane] = links[size_t(pl) * vh + s];
+      }
+    }
+  __syncthreads();
+  // 14-real Naik links: rebuild row 2 once per site (not once per rhs tile) into LDS planes of
+  // the arithmetic type after the stored planes, with the same arithmetic as load_link
+  C *row2 = reinterpret_cast<C *>(sl + PL * 64);
+  if constexpr (R14) {
+    for (int item = threadIdx.x; item < 8 * 64; item += 64 * WPB) {
+      const int k = item >> 6, ln = item & 63;
+      Lnk<Real> Lk;
+      load_link<Real, LT, true, false>(sl, link_plane(8 + k, recon), 64u, ln, Lk);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        C v;
+        v.x = Lk.re[2][b];
+        v.y = Lk.im[2][b];
+        row2[(k * 3 + b) * 64 + ln] = v;
+      }
+    }
+    __syncthreads();
+  }
+
+  // every lane computes: a lane past the last site works on site 0 (in-range addresses) and
+  // stores nothing
+  const unsigned sc = valid ? s : 0u;
+  int x, y, z, t;
+  {
+    const int xh = sc % g.lxh;
+    int rest = sc / g.lxh;
+    y = rest % g.ly;
+    rest /= g.ly;
+    z = rest % g.lz;
+    t = rest / g.lz;
+    x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+  }
+  const unsigned rowbase = sc - (x >> 1);
+
+  for (int tile = wave; tile < a.ntiles; tile += WPB) {
+    const int r0 = tile * RT;
+    int rr[RT];
+    bool ract[RT];
+    if (!tile_rhs<RT>(a, r0, rr, ract)) {  // the whole tile is inactive (uniform)
+      if constexpr (EPI) {
+        if (a.partial && lane == 0) {
+          const unsigned nw = (vh + 63) / 64;
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            if (r0 + r < a.n) a.partial[size_t(r0 + r) * nw + sblk] = 0.0;
+        }
+      }
+      continue;
+    }
+    const C *__restrict__ in = static_cast<const C *>(a.in) + size_t(r0) * 3 * vh;
+    Real acc_re[RT][3], acc_im[RT][3];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc_re[r][c] = acc_im[r][c] = Real(0);
+    // hop order as in k_dslash: per mu, fat fwd, fat bwd, Naik fwd, Naik bwd
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      unsigned f1, b1, f3, b3;
+      hop_sites(g, mu, sc, rowbase, x, y, z, t, f1, b1, f3, b3);
+      Lnk<Real> Lk;
+      load_link<Real, LT, false, false>(sl, link_plane(mu, recon), 64u, lane, Lk);
+      apply_hop_all<Real, RT, false>(Lk, in, vh, f1, rr, acc_re, acc_im);
+      load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
+      apply_hop_all<Real, RT, true>(Lk, in, vh, b1, rr, acc_re, acc_im);
+      load_naik_lds<Real, LT, R14>(sl, row2, mu, lane, Lk);
+      apply_hop_all<Real, RT, false>(Lk, in, vh, f3, rr, acc_re, acc_im);
+      load_naik_lds<Real, LT, R14>(sl, row2, 4 + mu, lane, Lk);
+      apply_hop_all<Real, RT, true>(Lk, in, vh, b3, rr, acc_re, acc_im);
+    }
+    bool act[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) act[r] = valid && ract[r];
+    store_tile<Real, RT, EPI>(a, r0, s, lane, sblk, act, acc_re, acc_im);
+  }
+}
+
 // Direction-pipelined LDS form: the workgroup (64 sites x WPB waves) stages the links of one
 // direction mu at a time -- X(x,mu), X(x-mu,mu)^dag, N(x,mu), N(x-3mu,mu)^dag -- in one of two
 // LDS buffers.  While the waves apply direction mu to their rhs tiles, the links of mu+1 are
@@ -590,7 +617,8 @@ __global__ void __launch_bounds__(64 * WPB, (WPB == 16 && TPW == 1) ? 8 : 1) k_d
   int sblk;
   if (!lds_block(a, sblk)) return;  // uniform for the whole workgroup
   const Geometry &g = a.g;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const unsigned vh = g.vh;
   const unsigned s = sblk * 64 + lane;
   const bool valid = s < vh;
@@ -638,29 +666,31 @@ __global__ void __launch_bounds__(64 * WPB, (WPB == 16 && TPW == 1) ? 8 : 1) k_d
     }
   };
 
-  int x = 0, y = 0, z = 0, t = 0;
-  if (valid) {
-    const int xh = s % g.lxh;
-    int rest = s / g.lxh;
+  // every lane computes: a lane past the last site works on site 0 and stores nothing
+  const unsigned sc = valid ? s : 0u;
+  int x, y, z, t;
+  {
+    const int xh = sc % g.lxh;
+    int rest = sc / g.lxh;
     y = rest % g.ly;
     rest /= g.ly;
     z = rest % g.lz;
     t = rest / g.lz;
     x = 2 * xh + ((y + z + t + a.out_parity) & 1);
   }
-  const unsigned rowbase = s - (x >> 1);
+  const unsigned rowbase = sc - (x >> 1);
 
-  bool act[TPW][RT];
+  int rr[TPW][RT];
+  bool ract[TPW][RT], tact[TPW];
   Real acc_re[TPW][RT][3], acc_im[TPW][RT][3];
 #pragma unroll
   for (int tw = 0; tw < TPW; ++tw) {
-    const int r0 = (wave + tw * WPB) * RT;
+    const int tile = wave + tw * WPB;
+    tact[tw] = tile < a.ntiles && tile_rhs<RT>(a, tile * RT, rr[tw], ract[tw]);
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      act[tw][r] = valid && (wave + tw * WPB < a.ntiles) && (r0 + r < a.n) && (!a.active || a.active[r0 + r]);
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc_re[tw][r][c] = acc_im[tw][r][c] = Real(0);
-    }
   }
 
   fetch(0);
@@ -671,68 +701,49 @@ __global__ void __launch_bounds__(64 * WPB, (WPB == 16 && TPW == 1) ? 8 : 1) k_d
   for (int mu = 0; mu < 4; ++mu) {
     const int buf = mu & 1;
     if (mu < 3) fetch(mu + 1);
-    if (valid) {
-      unsigned f1, b1, f3, b3;
-      if (mu == 0) {
-        const int xf1 = x + 1 >= g.lx ? x + 1 - g.lx : x + 1;
-        const int xb1 = x - 1 < 0 ? x - 1 + g.lx : x - 1;
-        const int xf3 = x + 3 >= g.lx ? x + 3 - g.lx : x + 3;
-        const int xb3 = x - 3 < 0 ? x - 3 + g.lx : x - 3;
-        f1 = rowbase + (xf1 >> 1);
-        b1 = rowbase + (xb1 >> 1);
-        f3 = rowbase + (xf3 >> 1);
-        b3 = rowbase + (xb3 >> 1);
+    unsigned f1, b1, f3, b3;
+    hop_sites(g, mu, sc, rowbase, x, y, z, t, f1, b1, f3, b3);
+    const LT *bl = sl + buf * BUF;
+#pragma unroll
+    for (int tw = 0; tw < TPW; ++tw) {
+      if (!tact[tw]) continue;  // uniform
+      const C *__restrict__ in = static_cast<const C *>(a.in) + size_t((wave + tw * WPB) * RT) * 3 * vh;
+      Lnk<Real> Lk;
+      load_link<Real, LT, false, false>(bl, 0, 64u, lane, Lk);
+      apply_hop_all<Real, RT, false>(Lk, in, vh, f1, rr[tw], acc_re[tw], acc_im[tw]);
+      load_link<Real, LT, false, false>(bl, 9, 64u, lane, Lk);
+      apply_hop_all<Real, RT, true>(Lk, in, vh, b1, rr[tw], acc_re[tw], acc_im[tw]);
+      if constexpr (!R14) {
+        load_link<Real, LT, false, false>(bl, 18, 64u, lane, Lk);
       } else {
-        const int c = mu == 1 ? y : (mu == 2 ? z : t);
-        const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
-        const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
-        f1 = s + (c + 1 >= L ? 1 - L : 1) * S;
-        b1 = s + (c - 1 < 0 ? L - 1 : -1) * S;
-        f3 = s + (c + 3 >= L ? 3 - L : 3) * S;
-        b3 = s + (c - 3 < 0 ? L - 3 : -3) * S;
-      }
-      const LT *bl = sl + buf * BUF;
 #pragma unroll
-      for (int tw = 0; tw < TPW; ++tw) {
-        if (wave + tw * WPB >= a.ntiles) continue;
-        const C *__restrict__ in = static_cast<const C *>(a.in) + size_t((wave + tw * WPB) * RT) * 3 * vh;
-        Lnk<Real> Lk;
-        load_link<Real, LT, false, false>(bl, 0, 64u, lane, Lk);
-        apply_hop<Real, RT, false>(Lk, in, vh, f1, act[tw], acc_re[tw], acc_im[tw]);
-        load_link<Real, LT, false, false>(bl, 9, 64u, lane, Lk);
-        apply_hop<Real, RT, true>(Lk, in, vh, b1, act[tw], acc_re[tw], acc_im[tw]);
-        if constexpr (!R14) {
-          load_link<Real, LT, false, false>(bl, 18, 64u, lane, Lk);
-        } else {
+        for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-          for (int ra = 0; ra < 2; ++ra)
+          for (int cb = 0; cb < 3; ++cb) ld_link<false>(bl + (18 + ra * 3 + cb) * 64 + lane, Lk.re[ra][cb], Lk.im[ra][cb]);
 #pragma unroll
-            for (int cb = 0; cb < 3; ++cb) ld_link<false>(bl + (18 + ra * 3 + cb) * 64 + lane, Lk.re[ra][cb], Lk.im[ra][cb]);
-#pragma unroll
-          for (int cb = 0; cb < 3; ++cb) {
-            const C v = row2[(buf * 6 + cb) * 64 + lane];
-            Lk.re[2][cb] = v.x;
-            Lk.im[2][cb] = v.y;
-          }
+        for (int cb = 0; cb < 3; ++cb) {
+          const C v = row2[(buf * 6 + cb) * 64 + lane];
+          Lk.re[2][cb] = v.x;
+          Lk.im[2][cb] = v.y;
         }
-        apply_hop<Real, RT, false>(Lk, in, vh, f3, act[tw], acc_re[tw], acc_im[tw]);
-        if constexpr (!R14) {
-          load_link<Real, LT, false, false>(bl, 27, 64u, lane, Lk);
-        } else {
-#pragma unroll
-          for (int ra = 0; ra < 2; ++ra)
-#pragma unroll
-            for (int cb = 0; cb < 3; ++cb)
-              ld_link<false>(bl + (18 + NS + ra * 3 + cb) * 64 + lane, Lk.re[ra][cb], Lk.im[ra][cb]);
-#pragma unroll
-          for (int cb = 0; cb < 3; ++cb) {
-            const C v = row2[(buf * 6 + 3 + cb) * 64 + lane];
-            Lk.re[2][cb] = v.x;
-            Lk.im[2][cb] = v.y;
-          }
-        }
-        apply_hop<Real, RT, true>(Lk, in, vh, b3, act[tw], acc_re[tw], acc_im[tw]);
       }
+      apply_hop_all<Real, RT, false>(Lk, in, vh, f3, rr[tw], acc_re[tw], acc_im[tw]);
+      if constexpr (!R14) {
+        load_link<Real, LT, false, false>(bl, 27, 64u, lane, Lk);
+      } else {
+#pragma unroll
+        for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+          for (int cb = 0; cb < 3; ++cb)
+            ld_link<false>(bl + (18 + NS + ra * 3 + cb) * 64 + lane, Lk.re[ra][cb], Lk.im[ra][cb]);
+#pragma unroll
+        for (int cb = 0; cb < 3; ++cb) {
+          const C v = row2[(buf * 6 + 3 + cb) * 64 + lane];
+          Lk.re[2][cb] = v.x;
+          Lk.im[2][cb] = v.y;
+        }
+      }
+      apply_hop_all<Real, RT, true>(Lk, in, vh, b3, rr[tw], acc_re[tw], acc_im[tw]);
     }
     if (mu < 3) {
       stash(buf ^ 1);
@@ -741,9 +752,26 @@ __global__ void __launch_bounds__(64 * WPB, (WPB == 16 && TPW == 1) ? 8 : 1) k_d
     }
   }
 #pragma unroll
-  for (int tw = 0; tw < TPW; ++tw)
-    if (wave + tw * WPB < a.ntiles)
-      store_tile<Real, RT, EPI>(a, (wave + tw * WPB) * RT, s, lane, sblk, act[tw], acc_re[tw], acc_im[tw]);
+  for (int tw = 0; tw < TPW; ++tw) {
+    const int tile = wave + tw * WPB;
+    if (tile >= a.ntiles) continue;
+    const int r0 = tile * RT;
+    if (!tact[tw]) {  // inactive tile: zero partials, nothing stored
+      if constexpr (EPI) {
+        if (a.partial && lane == 0) {
+          const unsigned nw = (vh + 63) / 64;
+#pragma unroll
+          for (int r = 0; r < RT; ++r)
+            if (r0 + r < a.n) a.partial[size_t(r0 + r) * nw + sblk] = 0.0;
+        }
+      }
+      continue;
+    }
+    bool act[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) act[r] = valid && ract[tw][r];
+    store_tile<Real, RT, EPI>(a, r0, s, lane, sblk, act, acc_re[tw], acc_im[tw]);
+  }
 }
 
 using DslashFn = void (*)(const Args &, dim3, hipStream_t);

@@ -292,3 +292,35 @@ def test_direction_pipelined_tile_limit(prec):
     m0, pq0 = lat.apply_m(prec, 0.1, v, with_pq=True)
     assert torch.equal(m1.view(torch.float32), m0.view(torch.float32)) and torch.equal(pq1, pq0)
     lat.close()
+
+
+def _tiled_links(dims, seed):
+    """A 4^4 seeded random field tiled over the lattice (only the sampled sites are checked, and
+    the oracle takes any links)."""
+    fat, naik = synth.gauge_links((4, 4, 4, 4), seed)
+    lx, ly, lz, lt = dims
+    reps = (lt // 4, lz // 4, ly // 4, lx // 4, 1, 1, 1)
+    tile = lambda u: np.ascontiguousarray(np.tile(u.reshape(4, 4, 4, 4, 4, 3, 3), reps).reshape(-1, 4, 3, 3))  # noqa: E731
+    return tile(fat), tile(naik)
+
+
+@pytest.mark.parametrize("name,prec,n", [("c3", hisq.HISQ_F32, 16), ("c3", hisq.HISQ_F16, 16),
+                                         ("c4", hisq.HISQ_F32, 32), ("c4", hisq.HISQ_F16, 32)])
+def test_full_size_48c12_64c16_sampled_sites(name, prec, n):
+    """The 48^3 x 12 and 64^3 x 16 lattices at their rhs counts, in the tuned launch
+    configuration of each: sampled output sites (including the first and last of each parity)
+    against the per-site oracle."""
+    dims = synth.WORKLOADS[name]["dims"]
+    fat, naik = _tiled_links(dims, 130)
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 18)
+    rng = np.random.default_rng(6)
+    sites = np.concatenate([[0, 1, lat.vh - 1], rng.choice(lat.vh, 24, replace=False)])
+    v = synth.sources(dims, n, 131)
+    tv = torch.from_numpy(v).to(DEV).to(torch.complex64)
+    print("launch", name, prec, n, hisq.hisq_get_launch(lat.ctx, prec, n, 0))
+    for par in (0, 1):
+        ref = oracle.dslash_sites(fat, naik, v, dims, par, sites)
+        got = lat.dslash(par, prec, tv).cpu().numpy()[:, :, sites]
+        assert rel_l2(got, ref) <= (2e-3 if prec == hisq.HISQ_F16 else 1e-6)
+    lat.close()

@@ -97,8 +97,8 @@ def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup
 STUDY = {
     "c3": dict(n_fcg=None, nsrc=16, nsnap=16, snap=60, harvest_tol=1e-8, epochs=20, plain=True),
     # 64^3 x 16: the network and its training scale with 16 x the vector volume, so the learned
-    # solve runs on 4 of the 32 rhs with 64 training pairs; the plain FP64 solve is left out
-    "c4": dict(n_fcg=4, nsrc=8, nsnap=8, snap=100, harvest_tol=1e-6, epochs=5, plain=False),
+    # solve runs on 2 of the 32 rhs with 64 training pairs; the plain FP64 solve is left out
+    "c4": dict(n_fcg=2, nsrc=8, nsnap=8, snap=100, harvest_tol=1e-6, epochs=20, plain=False),
 }
 
 
@@ -148,6 +148,7 @@ def solver_study(args, torch, synth, hisq, pm):
         return x, info
 
     solve("mixed_f16links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
+    solve("mixed_f32links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F32)
     if st["plain"]:
         solve("plain_f64", b, kind=hisq.HISQ_CG_F64)
     # training pairs along plain-CG trajectories of Gaussian sources
@@ -168,13 +169,25 @@ def solver_study(args, torch, synth, hisq, pm):
     hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, 4, 8, seed))
     hisq._check(lat.ctx, lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM))
     hisq._check(lat.ctx, lib.hisq_nn_set_loss(lat.ctx, hisq.HISQ_NN_LOSS_RESIDUAL, mass))
+    # start from the best multiple of the identity for the residual loss on the training
+    # residuals, c = sum <r, M r> / sum ||M r||^2 (P = N^dag N scales as |W_out|^2)
+    r32 = r[: min(16, npairs.value)].to(torch.complex64)
+    mr = lat.apply_m(hisq.HISQ_F32, mass, r32)
+    c = float(torch.sum((torch.conj(r32) * mr).real) / torch.sum(torch.abs(mr) ** 2))
+    del r32, mr
+    nparam = lib.hisq_nn_num_params(lat.ctx)
+    w = (ctypes.c_double * (2 * nparam))()
+    hisq._check(lat.ctx, lib.hisq_nn_get_params(lat.ctx, w, 2 * nparam))
+    for k in range(2 * (nparam - 8), 2 * nparam):
+        w[k] *= c ** 0.5
+    hisq._check(lat.ctx, lib.hisq_nn_set_params(lat.ctx, w, 2 * nparam))
     hist = (ctypes.c_double * epochs)()
     batch, lr = 16, 1e-2
     progress("train the network")
     t = time.perf_counter()
     hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
                                            epochs, batch, lr, seed, hist))
-    out["training"] = {"form": "gram", "loss": "residual", "epochs": epochs, "batch": batch,
+    out["training"] = {"form": "gram", "loss": "residual", "init_scale": round(c, 5), "epochs": epochs, "batch": batch,
                        "lr": lr, "bf16": True, "seconds": round(time.perf_counter() - t, 2),
                        "loss_first": round(hist[0], 5), "loss_last": round(hist[epochs - 1], 5)}
     del r, y
@@ -193,15 +206,47 @@ def solver_study(args, torch, synth, hisq, pm):
     torch.cuda.synchronize()
     out["network_apply_ms"] = {"n_rhs": nf, "ms": round(e0.elapsed_time(e1) / 5, 3)}
     del rv, zv
-    if nf != n:  # the mixed solver on the same bundle, for the iteration and time comparison
-        solve("mixed_f16links_fcg_bundle", bf, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
+    # the faster mixed solver is the reference of the learned one (on the same bundle)
+    best = min(("mixed_f16links", hisq.HISQ_F16), ("mixed_f32links", hisq.HISQ_F32),
+               key=lambda kv: out[kv[0]]["seconds"])
+    if nf != n:
+        solve(best[0] + "_fcg_bundle", bf, kind=hisq.HISQ_CG_MIXED, link_prec=best[1])
     solve("fcg_learned_f16links", bf, kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F16)
-    ref = out["mixed_f16links" if nf == n else "mixed_f16links_fcg_bundle"]
+    ref = out[best[0] if nf == n else best[0] + "_fcg_bundle"]
+    out["fcg_reference"] = best[0]
     if st["plain"]:
-        out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out["mixed_f16links"]["seconds"], 3)
+        out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out[best[0]]["seconds"], 3)
     out["speedup_fcg_vs_mixed"] = round(ref["seconds"] / out["fcg_learned_f16links"]["seconds"], 3)
     out["iteration_ratio_fcg_vs_mixed"] = round(out["fcg_learned_f16links"]["iters_mean"] / ref["iters_mean"], 3)
     lat.close()
+    return out
+
+
+def volume_sweep(hisq, torch, synth, pm):
+    """Half-Dslash time against the lattice volume (the paper reads its performance against the
+    lattice size at 4 rhs, Section 4), with 64^3 x 16 as the case no cache level holds: FP32 at
+    n = 4 and 16 on every lattice, FP16 links at n = 8 and 32 on 64^3 x 16."""
+    out = []
+    for dims in ((16, 16, 16, 16), (24, 24, 24, 24), (32, 32, 32, 8), (48, 48, 48, 12), (64, 64, 64, 16)):
+        fat, naik = synth.tiled_gauge_links(dims, 7)
+        lat = hisq.Lattice(dims, 0)
+        lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 18)
+        del fat, naik
+        cases = [(hisq.HISQ_F32, 4), (hisq.HISQ_F32, 16)]
+        if dims == (64, 64, 64, 16):
+            cases += [(hisq.HISQ_F16, 8), (hisq.HISQ_F16, 32)]
+        for prec, nn in cases:
+            a = torch.randn(nn, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
+            b = torch.randn(nn, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
+            _, ml = dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a), torch.empty_like(b), 10, 3)
+            byt = pm.half_dslash_bytes(lat.vh, nn, prec, 18)
+            out.append({"lattice": "x".join(map(str, dims)), "prec": "f32" if prec == hisq.HISQ_F32 else "f16links",
+                        "n": nn, "ms_per_launch": round(ml, 5),
+                        "gflops": round(pm.half_dslash_flops(lat.vh, nn) / (ml * 1e-3) / 1e9, 1),
+                        "compulsory_GBps": round(byt / (ml * 1e-3) / 1e9, 1),
+                        "launch": list(hisq.hisq_get_launch(lat.ctx, prec, nn, 0))})
+            del a, b
+        lat.close()
     return out
 
 
@@ -218,7 +263,7 @@ def main():
                     help="c1: Dslash throughput at 32^3x8 (default, the timed steps); c3/c4: the "
                          "solver comparison at 48^3x12 / 64^3x16 (plain FP64, mixed, learned FCG)")
     ap.add_argument("--epochs", type=int, default=0,
-                    help="training epochs of the solver study (0: 20 at 48^3x12, 5 at 64^3x16)")
+                    help="training epochs of the solver study (0: 20)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), then --steps FP32 Dslash steps")
@@ -322,6 +367,7 @@ def main():
             if recon == 14:
                 lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
         result["dslash_sweep"] = sweep
+        result["volume_sweep"] = volume_sweep(hisq, torch, synth, pm)
 
     if not args.no_cg:
         c2 = synth.WORKLOADS["c2"]

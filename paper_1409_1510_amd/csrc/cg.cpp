@@ -204,10 +204,10 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
         for (int i = 0; i < n; ++i) {
           if (!hS->active[i] || hS->replacements[i] == last_rep[i]) continue;
           last_rep[i] = hS->replacements[i];
-          if (hS->rr_true[i] < 0.25 * best[i]) {
+          if (hS->rr_true[i] < kStallDrop * best[i]) {
             best[i] = hS->rr_true[i];
             stale[i] = 0;
-          } else if (++stale[i] >= 6 && op_prec == HISQ_F16 && ctx->links[HISQ_F32].base) {
+          } else if (++stale[i] >= kStallUpdates && op_prec == HISQ_F16 && ctx->links[HISQ_F32].base) {
             op_prec = HISQ_F32;
             for (int k = 0; k < n; ++k) stale[k] = 0;
           }

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "cg_state.hpp"
@@ -145,6 +146,18 @@ __device__ inline float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// packed BF16 pairs (x = low half) and their FP32-accumulating dot product a.x b.x + a.y b.y + c
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline float dot2(unsigned a, unsigned b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), c, false);
+}
+__device__ inline unsigned pack_bf(float lo, float hi) {  // round to nearest even
+  bf16x2 v;
+  v.x = static_cast<__bf16>(lo);
+  v.y = static_cast<__bf16>(hi);
+  return __builtin_bit_cast(unsigned, v);
+}
+
 // stencil coefficient of hop h, channel c (the adjoint stencil uses conj(a[adj(h)]))
 template <bool ADJ>
 __device__ inline float2 coef(const float2 *__restrict__ a, int h, int c) {
@@ -243,10 +256,23 @@ struct FusedArgs {
 // run together share their sites' links through L2.
 template <typename AT, typename LT, bool ADJ, bool IN_VEC, bool OUT_VEC>
 __global__ void __launch_bounds__(kThreads) k_nn_layer(FusedArgs F) {
+  constexpr bool PK = std::is_same<AT, bf16>::value;  // BF16 storage: packed BF16 dot products
   const Geometry &g = F.A.g;
   const unsigned V = 2u * g.vh;
   const int b = blockIdx.x % F.A.batch;
   const unsigned X = (blockIdx.x / F.A.batch) * kThreads + threadIdx.x;
+  // BF16 mix: the C x C complex matrix as packed pairs, (Re m, -Im m) and (Im m, Re m)
+  __shared__ unsigned mixr[PK && !OUT_VEC ? NC * NC : 1], mixi[PK && !OUT_VEC ? NC * NC : 1];
+  if constexpr (PK && !OUT_VEC) {
+    if (threadIdx.x < NC * NC) {
+      const int p = threadIdx.x / NC, c = threadIdx.x % NC;
+      float2 m = F.mix_conjt ? F.w[c * NC + p] : F.w[p * NC + c];
+      if (F.mix_conjt) m.y = -m.y;
+      mixr[threadIdx.x] = pack_bf(m.x, -m.y);
+      mixi[threadIdx.x] = pack_bf(m.y, m.x);
+    }
+    __syncthreads();
+  }
   if (X >= F.out_sites) return;
   const Site q = decode(g, X);
   float acc[3][NR];
@@ -324,6 +350,40 @@ __global__ void __launch_bounds__(kThreads) k_nn_layer(FusedArgs F) {
             acc[i][2 * c + 1] = fmaf(w.x, ti, fmaf(w.y, tr, acc[i][2 * c + 1]));
           }
         }
+      } else if constexpr (PK) {
+        // (U v)_i of channel c as packed BF16 dot products: Re = (Re u, -Im u).(Re v, Im v),
+        // Im = (Im u, Re u).(Re v, Im v), accumulated in FP32
+        unsigned ur[3][3], ui[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            ur[i][j] = pack_bf(lr[i][j], -li[i][j]);
+            ui[i][j] = pack_bf(li[i][j], lr[i][j]);
+          }
+        unsigned vw[3][NC];
+#pragma unroll
+        for (int col = 0; col < 3; ++col) {
+          const uint4 *q4 = reinterpret_cast<const uint4 *>(ib + (size_t(col) * V + nb) * NR);
+          const uint4 t0 = q4[0], t1 = q4[1];
+          vw[col][0] = t0.x; vw[col][1] = t0.y; vw[col][2] = t0.z; vw[col][3] = t0.w;
+          vw[col][4] = t1.x; vw[col][5] = t1.y; vw[col][6] = t1.z; vw[col][7] = t1.w;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const float2 w = coef<ADJ>(F.a, h, c);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            float tr = 0.f, ti = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              tr = dot2(ur[i][j], vw[j][c], tr);
+              ti = dot2(ui[i][j], vw[j][c], ti);
+            }
+            acc[i][2 * c] = fmaf(w.x, tr, fmaf(-w.y, ti, acc[i][2 * c]));
+            acc[i][2 * c + 1] = fmaf(w.x, ti, fmaf(w.y, tr, acc[i][2 * c + 1]));
+          }
+        }
       } else {
         float v[3][NR];
 #pragma unroll
@@ -360,6 +420,39 @@ __global__ void __launch_bounds__(kThreads) k_nn_layer(FusedArgs F) {
         im = fmaf(wr, acc[col][2 * c + 1], fmaf(wi, acc[col][2 * c], im));
       }
       zb[size_t(col) * F.out_sites + X] = make_float2(re, im);
+    }
+  } else if constexpr (PK) {
+    // mix in packed BF16 (psi rounded to BF16, as the MFMA mixing of the training path does)
+    AT *ob = static_cast<AT *>(F.out) + size_t(b) * F.A.sample_stride;
+    unsigned pw[3][NC], ow[3][NC];
+#pragma unroll
+    for (int col = 0; col < 3; ++col)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) pw[col][c] = pack_bf(acc[col][2 * c], acc[col][2 * c + 1]);
+#pragma unroll 2
+    for (int p = 0; p < NC; ++p) {  // one matrix row at a time from LDS (broadcast reads)
+      unsigned mr[NC], mi[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        mr[c] = mixr[p * NC + c];
+        mi[c] = mixi[p * NC + c];
+      }
+#pragma unroll
+      for (int col = 0; col < 3; ++col) {
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          re = dot2(mr[c], pw[col][c], re);
+          im = dot2(mi[c], pw[col][c], im);
+        }
+        ow[col][p] = pack_bf(re, im);
+      }
+    }
+#pragma unroll
+    for (int col = 0; col < 3; ++col) {
+      uint4 *q4 = reinterpret_cast<uint4 *>(ob + (size_t(col) * V + X) * NR);
+      q4[0] = make_uint4(ow[col][0], ow[col][1], ow[col][2], ow[col][3]);
+      q4[1] = make_uint4(ow[col][4], ow[col][5], ow[col][6], ow[col][7]);
     }
   } else {
     AT *ob = static_cast<AT *>(F.out) + size_t(b) * F.A.sample_stride;
@@ -1592,10 +1685,10 @@ int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
       for (int i = 0; i < n; ++i) {
         if (hS->active[i] && hS->replacements[i] != last_rep[i]) {
           last_rep[i] = hS->replacements[i];
-          if (hS->rr_true[i] < 0.25 * best[i]) {
+          if (hS->rr_true[i] < kStallDrop * best[i]) {
             best[i] = hS->rr_true[i];
             stale[i] = 0;
-          } else if (++stale[i] >= 6) {
+          } else if (++stale[i] >= kStallUpdates) {
             fell[i] = 1;  // stagnation: hand this rhs to the mixed solver
           }
         }

@@ -11,7 +11,6 @@ import argparse
 import os
 import sys
 
-import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
@@ -23,17 +22,6 @@ from paper_1409_1510_amd import hisq  # noqa: E402
 RHS = {"c1": (1, 2, 4, 8, 16), "c2": (8,), "c3": (8, 16), "c4": (8, 32)}
 
 
-def tiled_links(dims):
-    small = (4, 4, 4, 4)
-    fat, naik = synth.gauge_links(small, 7)
-    lx, ly, lz, lt = dims
-    f = fat.reshape(4, 4, 4, 4, 4, 3, 3)
-    nk = naik.reshape(4, 4, 4, 4, 4, 3, 3)
-    reps = (lt // 4, lz // 4, ly // 4, lx // 4, 1, 1, 1)
-    return (np.ascontiguousarray(np.tile(f, reps).reshape(-1, 4, 3, 3)),
-            np.ascontiguousarray(np.tile(nk, reps).reshape(-1, 4, 3, 3)))
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=hisq.TUNING_PATH)
@@ -42,7 +30,7 @@ def main():
     os.environ["HISQ_AUTOTUNE"] = "1"
     for name in args.lattices.split(","):
         dims = synth.WORKLOADS[name]["dims"]
-        fat, naik = tiled_links(dims)
+        fat, naik = synth.tiled_gauge_links(dims, 7)
         for recon in (18, 14):
             lat = hisq.Lattice(dims, 0)
             lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL if recon == 18 else

@@ -109,6 +109,21 @@ def gauge_links(dims, seed: int, eps: float = 0.4, pert: float = 0.05, chunk: in
     return fat, naik
 
 
+def tiled_gauge_links(dims, seed: int, eps: float = 0.4):
+    """gauge_links on a 4^4 lattice, tiled periodically over `dims` (each extent a multiple of
+    4): a fast stand-in at large volumes where only timing or sampled sites matter."""
+    small = (4, 4, 4, 4)
+    fat, naik = gauge_links(small, seed, eps=eps)
+    lx, ly, lz, lt = dims
+    if lx % 4 or ly % 4 or lz % 4 or lt % 4:
+        raise ValueError("tiled links need every extent to be a multiple of 4")
+    reps = (lt // 4, lz // 4, ly // 4, lx // 4, 1, 1, 1)
+
+    def tile(u):
+        return np.ascontiguousarray(np.tile(u.reshape(4, 4, 4, 4, 4, 3, 3), reps).reshape(-1, 4, 3, 3))
+    return tile(fat), tile(naik)
+
+
 def sources(dims, n: int, seed: int, kind: str = "gaussian") -> np.ndarray:
     """n single-parity source vectors, [n][3][V/2] complex128."""
     check_dims(dims)

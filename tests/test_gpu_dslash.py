@@ -294,16 +294,6 @@ def test_direction_pipelined_tile_limit(prec):
     lat.close()
 
 
-def _tiled_links(dims, seed):
-    """A 4^4 seeded random field tiled over the lattice (only the sampled sites are checked, and
-    the oracle takes any links)."""
-    fat, naik = synth.gauge_links((4, 4, 4, 4), seed)
-    lx, ly, lz, lt = dims
-    reps = (lt // 4, lz // 4, ly // 4, lx // 4, 1, 1, 1)
-    tile = lambda u: np.ascontiguousarray(np.tile(u.reshape(4, 4, 4, 4, 4, 3, 3), reps).reshape(-1, 4, 3, 3))  # noqa: E731
-    return tile(fat), tile(naik)
-
-
 @pytest.mark.parametrize("name,prec,n", [("c3", hisq.HISQ_F32, 16), ("c3", hisq.HISQ_F16, 16),
                                          ("c4", hisq.HISQ_F32, 32), ("c4", hisq.HISQ_F16, 32)])
 def test_full_size_48c12_64c16_sampled_sites(name, prec, n):
@@ -311,7 +301,7 @@ def test_full_size_48c12_64c16_sampled_sites(name, prec, n):
     configuration of each: sampled output sites (including the first and last of each parity)
     against the per-site oracle."""
     dims = synth.WORKLOADS[name]["dims"]
-    fat, naik = _tiled_links(dims, 130)
+    fat, naik = synth.tiled_gauge_links(dims, 130)
     lat = hisq.Lattice(dims, 0)
     lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 18)
     rng = np.random.default_rng(6)

@@ -144,6 +144,7 @@ def solver_study(args, torch, synth, hisq, pm):
                       "converged": sum(info["converged"]), "fell_back": sum(info["fell_back"]),
                       "reliable_updates": info["reliable_updates"], "rc": info["rc"],
                       "peak_device_GB": round(info["peak_bytes"] / 1e9, 2),
+                      "fp32_links_from_iter": info["link_switch_iter"],
                       "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
         return x, info
 
@@ -388,9 +389,11 @@ def main():
             cg[name] = {"s_per_rhs": round(sec / c2["n"], 5), "seconds": round(sec, 4),
                         "iters_max": max(info["iters"]), "iters_min": min(info["iters"]),
                         "reliable_updates": info["reliable_updates"],
+                        "fp32_links_from_iter": info["link_switch_iter"],
                         "true_resid_max": max(info["true_resid"]), "rc": info["rc"],
                         "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
-        cg["speedup_mixed_vs_f64"] = round(cg["plain_f64"]["seconds"] / cg["mixed_f16links"]["seconds"], 3)
+        cg["speedup_mixed_vs_f64"] = round(cg["plain_f64"]["seconds"] / min(cg["mixed_f16links"]["seconds"],
+                                                                          cg["mixed_f32links"]["seconds"]), 3)
         result["cg"] = cg
         lat2.close()
 

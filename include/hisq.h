@@ -179,6 +179,8 @@ typedef struct {
   long long dslash_site_rhs; /* sum over half-Dslash launches of (sites x active rhs)           */
   double seconds;      /* wall time of the solve                                                 */
   size_t peak_bytes;   /* device workspace held by the context after the solve                   */
+  int link_switch_iter;/* MIXED with FP16 links: iteration at which the inner operator moved to   */
+                       /*    the FP32 links (-1: never); see hisq_cg_mrhs                        */
 } hisq_cg_stats;
 
 /* Solve M x_i = b_i (M = m^2 - D_eo D_oe on even sites) for n right-hand sides at once; each
@@ -188,8 +190,15 @@ typedef struct {
  *   HISQ_CG_F64   : FP64 throughout.
  *   HISQ_CG_MIXED : FP32 Dslash/BLAS body (links p->link_prec), FP64 solution accumulation, FP64
  *                   reductions, FP64 true-residual replacement every p->reliable_every iterations.
- *   HISQ_FCG_NN   : flexible CG preconditioned by the network of hisq_nn_init/hisq_nn_train;
- *                   falls back to MIXED for a rhs whose preconditioned step breaks down.
+ *                   With FP16 links the inner operator moves to the FP32 links (when loaded)
+ *                   once the FP16 error dominates: two replacements in a row where the true
+ *                   residual exceeds the iterated one by more than 2x in norm while the relative
+ *                   residual is still above 1e-5, or a stalled true residual.
+ *   HISQ_FCG_NN   : flexible CG preconditioned by the network of hisq_nn_init/hisq_nn_train
+ *                   (Notay's FCG with truncation 1, complex step sizes; FP32 body with
+ *                   p->link_prec links, FP64 reliable updates); a rhs whose preconditioned step
+ *                   breaks down, or whose true residual stops falling (6 replacements in a row
+ *                   without a 10 % drop), is finished by MIXED from its current x.
  * Synchronises.  Returns HISQ_ERR_NOCONV if some rhs missed tol within max_iter. */
 int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
                  const hisq_cg_params *p, hisq_cg_stats *stats);

@@ -264,6 +264,7 @@ __global__ void k_reduce_true(const double *__restrict__ partial, int nblk, CGSt
   if (threadIdx.x == 0) {
     S->rr_true[r] = v;
     if (final_only) return;
+    S->drift[r] = S->rr[r] > 0.0 ? v / S->rr[r] : 1.0;
     S->hit[r] = 0;
     S->replacements[r] += 1;
     if (!isfinite(v)) {

@@ -137,13 +137,14 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
 
   // host-side stagnation bookkeeping (mixed): best true residual and polls without progress
   double best[HISQ_MAX_RHS];
-  int stale[HISQ_MAX_RHS];
+  int stale[HISQ_MAX_RHS], drifting[HISQ_MAX_RHS];
   int last_rep[HISQ_MAX_RHS];
   for (int i = 0; i < n; ++i) {
     best[i] = hS->rr_true[i];
-    stale[i] = 0;
+    stale[i] = drifting[i] = 0;
     last_rep[i] = 0;
   }
+  int switch_iter = -1;
 
   auto reliable = [&](int all) -> int {
     RETCHK(cg_select(ctx, S, n, all));
@@ -198,19 +199,30 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
       }
       nactive = 0;
       for (int i = 0; i < n; ++i) nactive += hS->active[i];
-      if (mixed) {
-        // Stagnation of the true residual with FP16 links: switch the inner operator to FP32
-        // links (the FP16 operator error ~5e-4 can stall the reliable updates).
+      if (mixed && op_prec == HISQ_F16 && ctx->links[HISQ_F32].base) {
+        // FP16-link error dominating (the true residual drifts away from the iterated one well
+        // above the FP32 floor) or a stalled true residual: the inner operator moves to the FP32
+        // links for the rest of the solve (the FP16 rounding of ~5e-4 can slow CG a lot on
+        // ill-conditioned systems).
+        bool to_f32 = false;
         for (int i = 0; i < n; ++i) {
           if (!hS->active[i] || hS->replacements[i] == last_rep[i]) continue;
           last_rep[i] = hS->replacements[i];
+          if (hS->drift[i] > kDriftRatio && hS->rr_true[i] > kDriftFloor2 * hS->bnorm2[i]) {
+            to_f32 = to_f32 || ++drifting[i] >= kDriftUpdates;
+          } else {
+            drifting[i] = 0;
+          }
           if (hS->rr_true[i] < kStallDrop * best[i]) {
             best[i] = hS->rr_true[i];
             stale[i] = 0;
-          } else if (++stale[i] >= kStallUpdates && op_prec == HISQ_F16 && ctx->links[HISQ_F32].base) {
-            op_prec = HISQ_F32;
-            for (int k = 0; k < n; ++k) stale[k] = 0;
+          } else if (++stale[i] >= kStallUpdates) {
+            to_f32 = true;
           }
+        }
+        if (to_f32) {
+          op_prec = HISQ_F32;
+          switch_iter = it;
         }
       }
     }
@@ -224,6 +236,7 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
   if (st) {
     st->total_iters = it;
     st->reliable_updates = reps;
+    st->link_switch_iter = switch_iter;
     if (st->fell_back)
       for (int i = 0; i < n; ++i) st->fell_back[i] = 0;
   }
@@ -250,6 +263,7 @@ extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, vo
   if (prm->kind != HISQ_CG_F64 && !ctx->links[prm->link_prec].base)
     return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: link copy of the requested precision missing");
   HIPCHK(ctx, hipSetDevice(ctx->device));
+  if (st) st->link_switch_iter = -1;
   auto t0 = std::chrono::steady_clock::now();
   void *sp, *pp, *hp;
   RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));

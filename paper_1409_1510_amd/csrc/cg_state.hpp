@@ -12,6 +12,12 @@ enum { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2, CG_NONFINITE = 3 };
 // residual only ~1.5x per 300 iterations, so a stronger demand would flag normal progress.
 constexpr double kStallDrop = 0.9;
 constexpr int kStallUpdates = 6;
+// FP16-link error test of the mixed solver: the true residual exceeds the iterated one by more
+// than 2x in norm (4x squared) at kDriftUpdates replacements in a row while ||b - Mx|| / ||b||
+// is above 1e-5 (where FP32 vectors still track it closely).
+constexpr double kDriftRatio = 4.0;
+constexpr double kDriftFloor2 = 1e-10;
+constexpr int kDriftUpdates = 2;
 
 struct CGState {
   double rho[HISQ_MAX_RHS];      // <r, r> of the iterated residual (or <z, r> for FCG)
@@ -21,6 +27,7 @@ struct CGState {
   double bnorm2[HISQ_MAX_RHS];   // ||b||^2
   double rr[HISQ_MAX_RHS];       // ||r||^2 of the iterated residual
   double rr_true[HISQ_MAX_RHS];  // ||b - M x||^2 at the last FP64 recomputation
+  double drift[HISQ_MAX_RHS];    // ||b - M x||^2 / iterated ||r||^2 at the last recomputation
   double calpha[2 * HISQ_MAX_RHS]; // FCG: complex alpha = <p, r> / <p, q>  (re, im)
   double cbeta[2 * HISQ_MAX_RHS];  // FCG: complex beta = -<q, z> / <p, q>  (re, im)
   int active[HISQ_MAX_RHS];      // 1 while the rhs iterates

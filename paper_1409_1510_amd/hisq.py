@@ -73,7 +73,7 @@ class hisq_cg_stats(ctypes.Structure):
                 ("fell_back", ctypes.POINTER(ctypes.c_int)),
                 ("total_iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
                 ("dslash_site_rhs", ctypes.c_longlong), ("seconds", ctypes.c_double),
-                ("peak_bytes", ctypes.c_size_t)]
+                ("peak_bytes", ctypes.c_size_t), ("link_switch_iter", ctypes.c_int)]
 
 
 def header_functions() -> list[str]:
@@ -345,11 +345,11 @@ class Lattice:
         res = (ctypes.c_double * n)()
         conv = (ctypes.c_int * n)()
         fb = (ctypes.c_int * n)()
-        st = hisq_cg_stats(iters, res, conv, fb, 0, 0, 0, 0.0, 0)
+        st = hisq_cg_stats(iters, res, conv, fb, 0, 0, 0, 0.0, 0, -1)
         hisq_set_stream(self.ctx)
         rc = hisq_cg_mrhs(self.ctx, mass, n, b, x, p, st)
         info = dict(rc=rc, iters=list(iters), true_resid=list(res), converged=list(conv),
                     fell_back=list(fb), total_iters=st.total_iters,
                     reliable_updates=st.reliable_updates, dslash_site_rhs=st.dslash_site_rhs,
-                    seconds=st.seconds, peak_bytes=st.peak_bytes)
+                    seconds=st.seconds, peak_bytes=st.peak_bytes, link_switch_iter=st.link_switch_iter)
         return x, info

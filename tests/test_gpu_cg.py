@@ -126,3 +126,26 @@ def test_c2_mixed_fp16_links_full_size():
     print(f"c2 mixed: {im['seconds']:.3f}s iters {im['iters']} reps {im['reliable_updates']}; "
           f"fp64: {idd['seconds']:.3f}s iters {idd['iters']}")
     lat.close()
+
+
+def test_mixed_fp16_link_switch_is_reported():
+    """The mixed solver reports the iteration at which FP16 links gave way to FP32 links (-1:
+    never); with FP32 links it never switches, and both reach the true FP64 residual."""
+    dims, mass, tol = (8, 8, 8, 8), 0.01, 1e-8
+    lat, fat, naik = make_lattice(dims, 60)
+    b = synth.sources(dims, 4, 61)
+    tb = torch.from_numpy(b).to(DEV)
+    for link_prec in (hisq.HISQ_F32, hisq.HISQ_F16):
+        x, info = lat.cg(mass, tb, kind=hisq.HISQ_CG_MIXED, tol=tol, link_prec=link_prec, max_iter=40000)
+        assert info["rc"] == 0, info
+        res = oracle.true_residual(fat, naik, x.cpu().numpy(), b, dims, mass)
+        assert np.all(res <= tol)
+        sw = info["link_switch_iter"]
+        print(f"link_prec {link_prec}: iters {max(info['iters'])}, FP32 links from iteration {sw}")
+        if link_prec == hisq.HISQ_F32:
+            assert sw == -1
+        else:
+            assert sw == -1 or 0 <= sw <= info["total_iters"]
+    xf, info = lat.cg(mass, tb, kind=hisq.HISQ_CG_F64, tol=tol)
+    assert info["link_switch_iter"] == -1
+    lat.close()

@@ -149,3 +149,20 @@ def test_mixed_fp16_link_switch_is_reported():
     xf, info = lat.cg(mass, tb, kind=hisq.HISQ_CG_F64, tol=tol)
     assert info["link_switch_iter"] == -1
     lat.close()
+
+
+@pytest.mark.parametrize("link_prec", [hisq.HISQ_F32, hisq.HISQ_F16])
+def test_c3_mixed_full_size_true_residual(link_prec):
+    """48^3 x 12, m = 0.01, Z2 rhs (2 of the 16, to keep the CPU check short): the mixed solver
+    reaches a true FP64 residual <= 1e-8 as measured by the oracle's M on the GPU's solution."""
+    cfg = synth.WORKLOADS["c3"]
+    dims, mass, tol = cfg["dims"], cfg["mass"], cfg["tol"]
+    seed = synth.workload_seed("c3")
+    lat, fat, naik = make_lattice(dims, seed)
+    b = synth.sources(dims, 2, seed + 1, cfg["source"])
+    x, info = _solve(lat, mass, b, kind=hisq.HISQ_CG_MIXED, tol=tol, link_prec=link_prec, max_iter=40000)
+    assert info["rc"] == 0, info
+    res = oracle.true_residual(fat, naik, x, b, dims, mass)
+    print(f"c3 mixed link_prec {link_prec}: iters {info['iters']}, oracle residual {res}")
+    assert np.all(res <= tol)
+    lat.close()

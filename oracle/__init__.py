@@ -18,3 +18,4 @@ from .dslash import (  # noqa: F401
 )
 from .cg import cg, true_residual  # noqa: F401
 from . import nn  # noqa: F401
+from . import trace  # noqa: F401

@@ -11,7 +11,9 @@ Also reported on the same JSON line:
                   around each launch of the timed region, on the launch stream), against 8 TB/s;
   dslash_sweep  : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
   cg            : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
-                  the mixed-precision solver (FP16 links) and the plain FP64 solver;
+                  the mixed-precision solver (FP16 and FP32 links) and the plain FP64 solver;
+  trace_minv    : Tr M^-1 on the same lattice from 64 Z2 noise vectors (Eq. 2), with its error;
+  volume_sweep  : the FP32 half Dslash against the lattice volume;
   cpu_baseline  : the FP64 numpy oracle's half Dslash on a bounded sample of the same lattice.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-sweep]
@@ -395,6 +397,19 @@ def main():
         cg["speedup_mixed_vs_f64"] = round(cg["plain_f64"]["seconds"] / min(cg["mixed_f16links"]["seconds"],
                                                                           cg["mixed_f32links"]["seconds"]), 3)
         result["cg"] = cg
+        # Eq. 2: Tr M^-1 from Z2 noise bundles through the mixed solver
+        nvec, bundle = 64, 16
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        est, err, smp = lat2.trace_minv(c2["mass"], nvec, bundle=bundle, seed=synth.workload_seed("c2") + 3,
+                                        kind=hisq.HISQ_CG_MIXED, tol=c2["tol"], link_prec=hisq.HISQ_F16)
+        sec = time.perf_counter() - t
+        smp = np.array(smp)
+        result["trace_minv"] = {
+            "workload": "32x32x32x8, m=0.02, Z2 noise, bundles of 16, mixed CG (FP16 links) to 1e-8",
+            "vectors": nvec, "estimate": round(est, 3), "std_error": round(err, 3),
+            "std_error_vs_n": {str(k): round(float(smp[:k].std(ddof=1) / np.sqrt(k)), 3) for k in (16, 32, 64)},
+            "seconds": round(sec, 3), "s_per_vector": round(sec / nvec, 5)}
         lat2.close()
 
     if not args.no_cpu:

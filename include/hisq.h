@@ -269,6 +269,25 @@ int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b, double tol
 int hisq_nn_save(hisq_ctx *ctx, const char *path);
 int hisq_nn_load(hisq_ctx *ctx, const char *path);
 
+/* ---- stochastic trace (Section 1, Eq. 2) -----------------------------------------------------
+ * The observables of Eq. 1 are traces of products of M^-1, estimated with many random vectors.
+ * These two calls give the basic one, Tr M^-1 over the 3*V/2 components of the even sites:
+ *   estimate = (1/N) sum_k eta_k^dag M^-1 eta_k,  std_error = sample std / sqrt(N),
+ * with counter-based Z2 noise: component c = (k*3 + colour)*(V/2) + site of the noise stream is
+ * -1 if the top bit of the c-th SplitMix64 output for `seed` is set, else +1 (SplitMix64: output
+ * c = mix(seed + (c+1)*0x9E3779B97F4A7C15), Steele, Lea and Flood 2014). */
+
+/* Noise vectors k0 .. k0+n-1 into out (device [n][3][V/2] complex128, real +-1).  Asynchronous. */
+int hisq_z2_noise(hisq_ctx *ctx, unsigned long long seed, long long k0, int n, void *out);
+
+/* Estimate Tr M^-1 from n_vec noise vectors 0 .. n_vec-1, solved in bundles of `bundle` rhs by
+ * hisq_cg_mrhs with params p (use_x0 is ignored).  samples (host, n_vec doubles) may be NULL;
+ * estimate (host) is required; std_error (host) may be NULL.  The context owns the bundle
+ * buffers.  Synchronises.  Returns HISQ_ERR_NOCONV, with the estimate still written, if some
+ * solve missed tol. */
+int hisq_trace_minv(hisq_ctx *ctx, double mass, int n_vec, int bundle, unsigned long long seed,
+                    const hisq_cg_params *p, double *samples, double *estimate, double *std_error);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,7 @@ enum WsSlot {
   WS_CG0, WS_CG1, WS_CG2, WS_CG3, WS_CG4, WS_CG5, WS_CG6, WS_CG7,
   WS_NN0, WS_NN1, WS_NN2, WS_NN3, WS_NN4, WS_NN5, WS_NN6, WS_NN7,
   WS_TUNE0, WS_TUNE1, WS_TUNE2,  // launch-configuration tuning scratch (freed after tuning)
+  WS_TR0, WS_TR1, WS_TR2,        // trace estimator: noise bundle, solutions, dot results
   WS_COUNT
 };
 

@@ -131,6 +131,9 @@ def _load():
         "hisq_nn_set_form": (cint, [vp, cint]),
         "hisq_nn_set_loss": (cint, [vp, cint, cd]),
         "hisq_nn_harvest": (cint, [vp, cd, cint, vp, cd, cint, cint, vp, vp, ip]),
+        "hisq_z2_noise": (cint, [vp, ctypes.c_ulonglong, ctypes.c_longlong, cint, vp]),
+        "hisq_trace_minv": (cint, [vp, cd, cint, cint, ctypes.c_ulonglong, ctypes.POINTER(hisq_cg_params),
+                                   dp, dp, dp]),
         "hisq_nn_save": (cint, [vp, ctypes.c_char_p]),
         "hisq_nn_load": (cint, [vp, ctypes.c_char_p]),
     }
@@ -333,6 +336,23 @@ class Lattice:
         hisq_set_stream(self.ctx)
         hisq_dot_mrhs(self.ctx, prec, n, a, b, d)
         return self.torch.complex(d[0::2], d[1::2])
+
+    def z2_noise(self, seed, k0, n):
+        out = self.empty(n, HISQ_F64)
+        hisq_set_stream(self.ctx)
+        _check(self.ctx, _lib.hisq_z2_noise(self.ctx, seed, k0, n, _ptr(out)))
+        return out
+
+    def trace_minv(self, mass, n_vec, bundle=16, seed=1, kind=HISQ_CG_MIXED, tol=1e-8, max_iter=40000,
+                   reliable_every=50, link_prec=HISQ_F32):
+        """(estimate, std_error, samples) of Tr M^-1 from n_vec Z2 noise vectors."""
+        p = hisq_cg_params(kind, tol, max_iter, reliable_every, link_prec, 0, 0)
+        samples = (ctypes.c_double * n_vec)()
+        est, err = ctypes.c_double(), ctypes.c_double()
+        hisq_set_stream(self.ctx)
+        _check(self.ctx, _lib.hisq_trace_minv(self.ctx, mass, n_vec, bundle, seed, ctypes.byref(p), samples,
+                                              ctypes.byref(est), ctypes.byref(err)))
+        return est.value, err.value, list(samples)
 
     def cg(self, mass, b, kind=HISQ_CG_F64, tol=1e-10, max_iter=20000, reliable_every=50,
            link_prec=HISQ_F32, x0=None, check_every=0):

@@ -70,28 +70,38 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup):
-    """Time `steps` full Dslash applications (D_oe then D_eo) with HIP events on the launch
-    stream: a pair at the ends of the timed region (ms per step, event overhead included) and a
-    pair around every launch inside it (mean kernel duration, the figure a kernel trace gives)."""
+def dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o, steps, warmup, isolated=True):
+    """Time `steps` full Dslash applications (D_oe then D_eo) issued back to back, with one pair
+    of HIP events on the launch stream at the ends of the timed region: ms per step, and the
+    average launch duration as the region over its 2 * steps launches (launch gaps included).
+    With `isolated`, a second, separate pass brackets every launch with its own event pair; a
+    marker between kernels costs a few microseconds each, so that figure (the mean of the
+    bracketed launches) is reported beside the other, not used for it."""
     for _ in range(warmup):
         lat.dslash(1, prec, v_e, w_o)
         lat.dslash(0, prec, v_o, w_e)
     torch.cuda.synchronize()
-    ev = [_events(torch) for _ in range(2 * steps)]
     t0, t1 = _events(torch)
     t0.record()
-    for k in range(steps):
-        ev[2 * k][0].record()
+    for _ in range(steps):
         lat.dslash(1, prec, v_e, w_o)
-        ev[2 * k][1].record()
-        ev[2 * k + 1][0].record()
         lat.dslash(0, prec, v_o, w_e)
-        ev[2 * k + 1][1].record()
     t1.record()
     torch.cuda.synchronize()
-    per_launch = [a.elapsed_time(b) for a, b in ev]
-    return t0.elapsed_time(t1) / steps, float(np.mean(per_launch))
+    ms_step = t0.elapsed_time(t1) / steps
+    ms_iso = None
+    if isolated:
+        ev = [_events(torch) for _ in range(2 * steps)]
+        for k in range(steps):
+            ev[2 * k][0].record()
+            lat.dslash(1, prec, v_e, w_o)
+            ev[2 * k][1].record()
+            ev[2 * k + 1][0].record()
+            lat.dslash(0, prec, v_o, w_e)
+            ev[2 * k + 1][1].record()
+        torch.cuda.synchronize()
+        ms_iso = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    return ms_step, ms_step / 2, ms_iso
 
 
 # per-study settings: rhs of the FCG solve, training sources x snapshots (every `snap` plain-CG
@@ -241,7 +251,8 @@ def volume_sweep(hisq, torch, synth, pm):
         for prec, nn in cases:
             a = torch.randn(nn, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
             b = torch.randn(nn, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
-            _, ml = dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a), torch.empty_like(b), 10, 3)
+            _, ml, _ = dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a), torch.empty_like(b),
+                                          10, 3, isolated=False)
             byt = pm.half_dslash_bytes(lat.vh, nn, prec, 18)
             out.append({"lattice": "x".join(map(str, dims)), "prec": "f32" if prec == hisq.HISQ_F32 else "f16links",
                         "n": nn, "ms_per_launch": round(ml, 5),
@@ -304,16 +315,16 @@ def main():
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
-        _, ms_launch = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
-                                          args.steps, 0)
+        _, ms_launch, _ = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
+                                             args.steps, 0, isolated=False)
         print(f"profile run done: {args.steps} steps, {n} rhs, lattice {dims}, launch "
               f"{hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)}, source {kernel_source_hash()}, "
-              f"event-timed {ms_launch * 1e3:.1f} us per launch")
+              f"region-timed average {ms_launch * 1e3:.1f} us per launch")
         lat.close()
         return
 
-    ms_step, ms_launch = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
-                                            args.steps, args.warmup)
+    ms_step, ms_launch, ms_iso = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
+                                                    args.steps, args.warmup)
     launch_cfg = hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)
     flops_step = 2 * pm.half_dslash_flops(vh, n)
     gflops = flops_step / (ms_step * 1e-3) / 1e9
@@ -344,7 +355,8 @@ def main():
                                        "nontemporal_links": launch_cfg[2], "lds_links": launch_cfg[3],
                                        "xcd_map": launch_cfg[4]},
                      "kernel_source_sha256_16": kernel_source_hash(),
-                     "bytes_per_launch": bytes_launch, "ms_per_launch": round(ms_launch, 5)},
+                     "bytes_per_launch": bytes_launch, "ms_per_launch": round(ms_launch, 5),
+                     "ms_per_launch_event_bracketed": round(ms_iso, 5)},
     }
 
     if not args.no_sweep:
@@ -358,8 +370,8 @@ def main():
                 dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
                 a = torch.from_numpy(synth.sources(dims, nn, 9)).to("cuda:0").to(dt)
                 b = torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0").to(dt)
-                ms, ml = dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a),
-                                            torch.empty_like(b), 10, 3)
+                ms, ml, _ = dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a),
+                                               torch.empty_like(b), 10, 3, isolated=False)
                 byt = pm.half_dslash_bytes(vh, nn, prec, recon)
                 lb, vb = pm.PREC_BYTES[prec]
                 paper_b = vh * (pm.link_reals(recon if prec else 18) * lb + nn * 17 * 6 * vb)

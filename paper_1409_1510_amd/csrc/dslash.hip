@@ -31,7 +31,7 @@ size_t lds_bytes(int prec, int recon, const hisq_launch &c) {
   if (c.lds_links >= 4)  // two buffers of one direction's planes (+ rebuilt Naik rows)
     return 2 * size_t(r14 ? 32 : 36) * 64 * elem + (r14 ? size_t(12) * 64 * 8 : 0);
   const size_t row2 = r14 ? size_t(24) * 64 * 8 : 0;
-  return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem + row2;
+  return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem + row2 + dslash::kNbrTableBytes;
 }
 
 bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size_t lds_max = 0) {
@@ -128,7 +128,9 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
     return set_err(ctx, HISQ_ERR_ARG, "the LDS Dslash forms need rhs_per_thread * 24 * V/2 < 4 GiB");
   if (c.xcd_map && geo.xmap != c.xcd_map) return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
-         mass2, pvec, partial, active, geo.xmap, geo.zmap_bps, geo.zmap_zr};
+         mass2, pvec, partial, active, geo.xmap, geo.zmap_bps, geo.zmap_zr,
+         dslash::make_fastdiv(unsigned(ctx->g.lxh)), dslash::make_fastdiv(unsigned(ctx->g.ly)),
+         dslash::make_fastdiv(unsigned(ctx->g.lz))};
   fn(a, dim3(geo.grid), ctx->stream);
   LAUNCHCHK(ctx, "k_dslash");
   return HISQ_OK;

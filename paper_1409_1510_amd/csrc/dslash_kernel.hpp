@@ -160,6 +160,40 @@ __device__ inline void apply_hop_all(const Lnk<Real> &L, const typename CT<Real>
   }
 }
 
+// apply_hop_all for FP32 vectors with the gathers as raw buffer loads: the tile's colour planes
+// are one buffer (wave-uniform descriptor), the neighbour is a byte offset within a plane (the
+// lane's only address operand) and the plane start a scalar offset, so a gather costs no
+// vector address arithmetic.  Buffer range checking returns 0 past the tile instead of
+// reading beyond it.
+typedef unsigned v2u_t __attribute__((__vector_size__(8)));
+template <int RT, bool NEG>
+__device__ inline void apply_hop_buf(const Lnk<float> &L, __amdgpu_buffer_rsrc_t rs, unsigned plane_bytes,
+                                     unsigned off, const int (&rr)[RT], float (&acc_re)[RT][3],
+                                     float (&acc_im)[RT][3]) {
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    float2 v[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const v2u_t u = __builtin_amdgcn_raw_buffer_load_b64(rs, off, unsigned(rr[r] * 3 + b) * plane_bytes, 0);
+      v[b].x = __uint_as_float(u[0]);
+      v[b].y = __uint_as_float(u[1]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const float lr = NEG ? -L.re[a][b] : L.re[a][b];
+        const float li = NEG ? -L.im[a][b] : L.im[a][b];
+        acc_re[r][a] = fmaR(lr, v[b].x, acc_re[r][a]);
+        acc_re[r][a] = fmaR(-li, v[b].y, acc_re[r][a]);
+        acc_im[r][a] = fmaR(lr, v[b].y, acc_im[r][a]);
+        acc_im[r][a] = fmaR(li, v[b].x, acc_im[r][a]);
+      }
+    }
+  }
+}
+
 // Neighbour indices (within the input parity) of output site s at coordinates (x, y, z, t) for
 // the four hops of direction mu: +1, -1, +3, -3.
 __device__ inline void hop_sites(const Geometry &g, int mu, unsigned s, unsigned rowbase, int x, int y, int z, int t,
@@ -184,6 +218,42 @@ __device__ inline void hop_sites(const Geometry &g, int mu, unsigned s, unsigned
   }
 }
 
+// Unsigned division by a run-time constant d with a multiply-high, two shifts and two adds
+// (Granlund and Montgomery, "Division by invariant integers using multiplication", 1994, the
+// unsigned round-up method): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, and
+// q = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0) with t = mulhi(m, n), exact for every
+// 32-bit n.  The lattice extents are divisors of this kind; the multipliers are set on the host.
+struct FastDiv {
+  unsigned m;
+  int s1, s2;
+};
+inline FastDiv make_fastdiv(unsigned d) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  const unsigned long long m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return FastDiv{unsigned(m), l < 1 ? l : 1, l > 1 ? l - 1 : 0};
+}
+__device__ inline unsigned fast_div(unsigned n, const FastDiv &f) {
+  const unsigned t = __umulhi(f.m, n);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// Neighbour index (within the input parity) of output site s at (x, y, z, t) for the hop of
+// direction mu by d = +1, -1, +3 or -3 (one periodic wrap: every extent is at least 4); the same
+// values as hop_sites.
+__device__ inline unsigned hop_site(const Geometry &g, int mu, int d, unsigned s, unsigned rowbase, int x, int y,
+                                    int z, int t) {
+  if (mu == 0) {
+    const int xn = x + d;
+    return rowbase + ((xn < 0 ? xn + g.lx : (xn >= g.lx ? xn - g.lx : xn)) >> 1);
+  }
+  const int c = mu == 1 ? y : (mu == 2 ? z : t);
+  const int L = mu == 1 ? g.ly : (mu == 2 ? g.lz : g.lt);
+  const int S = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+  const int cn = c + d;
+  return s + (cn < 0 ? d + L : (cn >= L ? d - L : d)) * S;
+}
+
 // Rhs of tile r0 a wave computes: rr[r] (clamped to the last rhs), ract[r] (rhs active);
 // returns whether any rhs of the tile is active.  All values are uniform across the wave.
 struct Args {
@@ -203,6 +273,7 @@ struct Args {
   int xmap;               // LDS form, XCD map: 0 contiguous ranges, 1 z slabs, 2 y slabs
   int zmap_bps;           //   64-site blocks per (z, t) plane
   int zmap_zr;            //   z-slab map: z slices owned by each XCD (Lz / 8)
+  FastDiv div_xh, div_y, div_z;  // division by Lx/2, Ly, Lz (site decoding of the LDS form)
 };
 
 template <int RT>
@@ -346,6 +417,18 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
   }
 }
 
+// Word 3 of a raw buffer descriptor on CDNA (32-bit data format, no swizzle, no stride): a
+// plain byte-addressed range checked against its size.
+constexpr int kBufWord3 = 0x00020000;
+
+// LDS of the whole-site form: the stored link planes of 64 sites, for 14-real Naik links the
+// 8 x 3 rebuilt row-2 entries in the arithmetic type, then the neighbour table (16 byte
+// offsets per site).
+constexpr size_t kNbrTableBytes = size_t(16) * 64 * sizeof(unsigned);
+template <typename Real, typename LT, bool R14> constexpr size_t lds_nbr_offset() {
+  return size_t(R14 ? 128 : 144) * 64 * sizeof(LT) + (R14 ? size_t(24) * 64 * sizeof(typename CT<Real>::T) : 0);
+}
+
 // Site block of an LDS-form workgroup under the XCD map of the launch (false: none).
 __device__ inline bool lds_block(const Args &a, int &sblk) {
   const Geometry &g = a.g;
@@ -481,9 +564,9 @@ template <bool NT> __device__ inline __half2 ld_raw(const __half2 *p) {
 // found in L2 than when every thread holds all n rhs; the links still come from HBM once.
 // Same site order, hop order and FMA sequence per rhs as k_dslash (bit-identical output), and
 // the same per-64-site grouping of the fused <p, Mp> partials.
-// (16 waves: at most 64 VGPRs, so that two workgroups share a CU)
+// (16 waves: at most 64 VGPRs, 8 waves: at most 128, so that two workgroups share a CU)
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
-__global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : 1) k_dslash_lds(Args a) {
+__global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : (WPB == 8 ? 2 : 1)) k_dslash_lds(Args a) {
   static_assert(WPB == 4 || WPB == 8 || WPB == 16, "4, 8 or 16 waves per workgroup");
   using C = typename CT<Real>::T;
   constexpr int recon = R14 ? 14 : 18;
@@ -499,24 +582,47 @@ __global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : 1) k_dslash_lds(Args
   const unsigned s = sblk * 64 + lane;
   const bool valid = s < vh;
   const LT *__restrict__ links = static_cast<const LT *>(a.links);
-  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access).  With
-  // NT the global loads carry the non-temporal hint, so the streamed links do not push the
-  // neighbour vectors out of L2.
-  for (int pl = wave; pl < PL; pl += WPB)
-    if (valid) {
-      if constexpr (NT) {
-        if constexpr (sizeof(LT) == 8) {
-          const unsigned long long u =
-              __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(links + size_t(pl) * vh + s));
-          *reinterpret_cast<unsigned long long *>(sl + pl * 64 + lane) = u;
-        } else {
-          const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(links + size_t(pl) * vh + s));
-          *reinterpret_cast<unsigned *>(sl + pl * 64 + lane) = u;
-        }
-      } else {
-        sl[pl * 64 + lane] = links[size_t(pl) * vh + s];
-      }
+  // every lane computes: a lane past the last site works on site 0 (in-range addresses) and
+  // stores nothing
+  const unsigned sc = valid ? s : 0u;
+  // stage the links of the 64 sites: plane-major, lane-minor (conflict-free LDS access); each
+  // wave issues a batch of CH plane loads before it writes any of them, so their latencies
+  // overlap.  With NT the global loads carry the non-temporal hint, so the streamed links do
+  // not push the neighbour vectors out of L2.
+  {
+    static_assert(PL % WPB == 0, "planes divide evenly among the waves");
+    constexpr int PPW = PL / WPB;
+    constexpr int CH = PPW % 9 == 0 ? 9 : 8;
+    static_assert(PPW % CH == 0, "whole batches");
+#pragma unroll 1
+    for (int c0 = 0; c0 < PPW; c0 += CH) {
+      LT v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) v[i] = ld_raw<NT>(links + size_t(wave + (c0 + i) * WPB) * vh + sc);
+#pragma unroll
+      for (int i = 0; i < CH; ++i) sl[(wave + (c0 + i) * WPB) * 64 + lane] = v[i];
     }
+  }
+  // neighbour table: the byte offsets (within a colour plane) of the 16 neighbours of the 64
+  // sites, [mu][site][+1, -1, +3, -3], built once per workgroup (one hop per wave and lane with
+  // 16 waves) so the rhs-tile loop does no site arithmetic
+  unsigned *nbt = reinterpret_cast<unsigned *>(smem_raw + lds_nbr_offset<Real, LT, R14>());
+  {
+    const unsigned q1 = fast_div(sc, a.div_xh);
+    const unsigned q2 = fast_div(q1, a.div_y);
+    const unsigned q3 = fast_div(q2, a.div_z);
+    const int xh = int(sc - q1 * unsigned(g.lxh));
+    const int y = int(q1 - q2 * unsigned(g.ly));
+    const int z = int(q2 - q3 * unsigned(g.lz));
+    const int t = int(q3);
+    const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+    const unsigned rowbase = sc - unsigned(xh);
+    for (int h = wave; h < 16; h += WPB) {
+      const int mu = h >> 2, k = h & 3;
+      const int d = k == 0 ? 1 : (k == 1 ? -1 : (k == 2 ? 3 : -3));
+      nbt[(mu * 64 + lane) * 4 + k] = hop_site(g, mu, d, sc, rowbase, x, y, z, t) * unsigned(sizeof(C));
+    }
+  }
   __syncthreads();
   // 14-real Naik links: rebuild row 2 once per site (not once per rhs tile) into LDS planes of
   // the arithmetic type after the stored planes, with the same arithmetic as load_link
@@ -537,21 +643,9 @@ __global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : 1) k_dslash_lds(Args
     __syncthreads();
   }
 
-  // every lane computes: a lane past the last site works on site 0 (in-range addresses) and
-  // stores nothing
-  const unsigned sc = valid ? s : 0u;
-  int x, y, z, t;
-  {
-    const int xh = sc % g.lxh;
-    int rest = sc / g.lxh;
-    y = rest % g.ly;
-    rest /= g.ly;
-    z = rest % g.lz;
-    t = rest / g.lz;
-    x = 2 * xh + ((y + z + t + a.out_parity) & 1);
-  }
-  const unsigned rowbase = sc - (x >> 1);
-
+  static_assert(sizeof(Real) == 4, "the LDS forms compute in FP32");
+  // a tile spans RT * 3 colour planes of less than 4 GiB in all (checked at launch)
+  const unsigned plane_bytes = vh * unsigned(sizeof(C));
   for (int tile = wave; tile < a.ntiles; tile += WPB) {
     const int r0 = tile * RT;
     int rr[RT];
@@ -567,7 +661,9 @@ __global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : 1) k_dslash_lds(Args
       }
       continue;
     }
-    const C *__restrict__ in = static_cast<const C *>(a.in) + size_t(r0) * 3 * vh;
+    const char *in = static_cast<const char *>(a.in) + size_t(r0) * 3 * plane_bytes;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(in), short(0), int(RT * 3 * plane_bytes), kBufWord3);
     Real acc_re[RT][3], acc_im[RT][3];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -576,17 +672,16 @@ __global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : 1) k_dslash_lds(Args
     // hop order as in k_dslash: per mu, fat fwd, fat bwd, Naik fwd, Naik bwd
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
-      unsigned f1, b1, f3, b3;
-      hop_sites(g, mu, sc, rowbase, x, y, z, t, f1, b1, f3, b3);
+      const uint4 nb = reinterpret_cast<const uint4 *>(nbt)[mu * 64 + lane];
       Lnk<Real> Lk;
       load_link<Real, LT, false, false>(sl, link_plane(mu, recon), 64u, lane, Lk);
-      apply_hop_all<Real, RT, false>(Lk, in, vh, f1, rr, acc_re, acc_im);
+      apply_hop_buf<RT, false>(Lk, rs, plane_bytes, nb.x, rr, acc_re, acc_im);
       load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
-      apply_hop_all<Real, RT, true>(Lk, in, vh, b1, rr, acc_re, acc_im);
+      apply_hop_buf<RT, true>(Lk, rs, plane_bytes, nb.y, rr, acc_re, acc_im);
       load_naik_lds<Real, LT, R14>(sl, row2, mu, lane, Lk);
-      apply_hop_all<Real, RT, false>(Lk, in, vh, f3, rr, acc_re, acc_im);
+      apply_hop_buf<RT, false>(Lk, rs, plane_bytes, nb.z, rr, acc_re, acc_im);
       load_naik_lds<Real, LT, R14>(sl, row2, 4 + mu, lane, Lk);
-      apply_hop_all<Real, RT, true>(Lk, in, vh, b3, rr, acc_re, acc_im);
+      apply_hop_buf<RT, true>(Lk, rs, plane_bytes, nb.w, rr, acc_re, acc_im);
     }
     bool act[RT];
 #pragma unroll
@@ -783,9 +878,7 @@ void launch_t(const Args &a, dim3 grid, hipStream_t st) {
 
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
 void launch_lds(const Args &a, dim3 grid, hipStream_t st) {
-  // 14-real Naik: the stored planes plus 8 x 3 rebuilt row-2 entries in the arithmetic type
-  constexpr size_t lds = size_t(R14 ? 128 : 144) * 64 * sizeof(LT) +
-                         (R14 ? size_t(24) * 64 * sizeof(typename CT<Real>::T) : 0);
+  constexpr size_t lds = lds_nbr_offset<Real, LT, R14>() + kNbrTableBytes;
   k_dslash_lds<Real, LT, RT, R14, EPI, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
 }
 
@@ -826,12 +919,15 @@ DslashFn pick_lds_rt(int rt) {
 // lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves, 3 = 16 waves
 template <typename Real, typename LT, bool R14, bool EPI, bool NT>
 DslashFn pick_lds(int rt, int lds) {
-  if constexpr (sizeof(LT) > 8) return nullptr;  // FP64 links do not fit LDS twice per CU
-  else if (lds >= 4) return pick_mu<Real, LT, R14, EPI, NT>(rt, lds);
-  if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
-  if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
-  if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);
-  return nullptr;
+  if constexpr (sizeof(LT) > 8) {  // FP64 links do not fit LDS twice per CU
+    return nullptr;
+  } else {
+    if (lds >= 4) return pick_mu<Real, LT, R14, EPI, NT>(rt, lds);
+    if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
+    if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
+    if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);
+    return nullptr;
+  }
 }
 
 template <typename Real, typename LT, bool R14, bool EPI, int SPB, bool NT>

@@ -281,6 +281,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), then --steps FP32 Dslash steps")
+    ap.add_argument("--profile-cg", action="store_true",
+                    help="short run for rocprofv3: the 32^3x8 mixed CG (FP16 links, 8 rhs) of the "
+                         "benchmark, solved twice")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver works on a single device (the multi-GPU "
@@ -294,6 +297,22 @@ def main():
     from paper_1409_1510_amd import perfmodel as pm
 
     torch.cuda.set_device(0)
+    if args.profile_cg:
+        c2 = synth.WORKLOADS["c2"]
+        fat2, naik2 = synth.gauge_links(c2["dims"], synth.workload_seed("c2"), eps=c2["eps"])
+        lat2 = hisq.Lattice(c2["dims"], 0)
+        lat2.load_links(fat2, naik2)
+        b = torch.from_numpy(synth.sources(c2["dims"], c2["n"], synth.workload_seed("c2") + 1)).to("cuda:0")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = lat2.cg(c2["mass"], b, tol=c2["tol"], max_iter=40000, kind=hisq.HISQ_CG_MIXED,
+                              link_prec=hisq.HISQ_F16)
+            torch.cuda.synchronize()
+            print(f"profile-cg solve: {time.perf_counter() - t:.3f} s, {max(info['iters'])} iterations",
+                  flush=True)
+        lat2.close()
+        return
     if args.workload in ("c3", "c4"):
         print(json.dumps(solver_study(args, torch, synth, hisq, pm)))
         return

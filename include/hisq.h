@@ -128,8 +128,8 @@ typedef struct {
   int nontemporal_links; /* 1: link loads carry the non-temporal cache hint                     */
   int lds_links;         /* 1, 2, 3: a workgroup of 64 sites x 4, 8, 16 waves stages its sites'  */
                          /*    links in LDS and its waves loop over the rhs tiles (requires      */
-                         /*    sites_per_block = 64, rhs_per_thread <= 4 (<= 2 for 16 waves) and */
-                         /*    LDS for 64 sites' links: not FP64);                               */
+                         /*    sites_per_block = 64, rhs_per_thread <= 4 (<= 2 for 16 waves);    */
+                         /*    FP64 links take a CU's LDS alone, FP32/FP16 links fit twice);     */
                          /* 4, 5, 6: the same with the links staged one direction at a time in  */
                          /*    two LDS buffers, the next direction loading while the current one */
                          /*    is applied; 16 waves x 1 rhs tile (4), 16 x 2 (5), 8 x 2 (6), so  */

@@ -56,9 +56,10 @@ int max_tiles(const hisq_launch &c) {
 bool fits_n(const hisq_launch &c, int n) {
   return (n + c.rhs_per_thread - 1) / c.rhs_per_thread <= max_tiles(c);
 }
-// the LDS forms address a rhs tile with 32-bit byte offsets (FP32 vectors)
-bool fits_lattice(const hisq_launch &c, const Geometry &g) {
-  return !c.lds_links || size_t(c.rhs_per_thread) * 3 * size_t(g.vh) * 8 < (size_t(1) << 32);
+// the LDS forms address a rhs tile with 32-bit byte offsets
+bool fits_lattice(const hisq_launch &c, const Geometry &g, int prec) {
+  const size_t elem = prec == HISQ_F64 ? 16 : 8;
+  return !c.lds_links || size_t(c.rhs_per_thread) * 3 * size_t(g.vh) * elem < (size_t(1) << 32);
 }
 
 int next_pow2(int n) {
@@ -124,8 +125,8 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
   const Geo geo = geometry(ctx->g, n, c);
   if (!fits_n(c, n))
     return set_err(ctx, HISQ_ERR_ARG, "this Dslash form holds at most %d rhs tiles (n = %d)", max_tiles(c), n);
-  if (!fits_lattice(c, ctx->g))
-    return set_err(ctx, HISQ_ERR_ARG, "the LDS Dslash forms need rhs_per_thread * 24 * V/2 < 4 GiB");
+  if (!fits_lattice(c, ctx->g, prec))
+    return set_err(ctx, HISQ_ERR_ARG, "the LDS Dslash forms need rhs_per_thread * 3 * V/2 * (vector element size) < 4 GiB");
   if (c.xcd_map && geo.xmap != c.xcd_map) return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
          mass2, pvec, partial, active, geo.xmap, geo.zmap_bps, geo.zmap_zr,
@@ -190,7 +191,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
           for (int xm : {0, 1, 2}) {
             hisq_launch c{rt, spb, nt, lds, xm};
             if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
-            if (!map_possible(g, xm) || !fits_n(c, n) || !fits_lattice(c, g)) continue;
+            if (!map_possible(g, xm) || !fits_n(c, n) || !fits_lattice(c, g, prec)) continue;
             float ms;
             rc = time_cfg(c, 3, &ms);
             if (rc != HISQ_OK) break;
@@ -278,8 +279,9 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
     if (!fits_n(c, n))
       return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: this form holds at most %d rhs tiles (n = %d)",
                      max_tiles(c), n);
-    if (!fits_lattice(c, ctx->g))
-      return set_err(ctx, HISQ_ERR_ARG, "hisq_set_launch: the LDS forms need rhs_per_thread * 24 * V/2 < 4 GiB");
+    if (!fits_lattice(c, ctx->g, prec))
+      return set_err(ctx, HISQ_ERR_ARG,
+                     "hisq_set_launch: the LDS forms need rhs_per_thread * 3 * V/2 * (vector element size) < 4 GiB");
     t.cfg = c;
     t.state = TuneEntry::FORCED;
   }
@@ -355,7 +357,7 @@ extern "C" int hisq_load_tuning(hisq_ctx *ctx, const char *path, int *n_loaded) 
     if (prec < 0 || prec > 2 || n < 1 || n > HISQ_MAX_RHS || (e != 0 && e != 1)) continue;
     if (!ctx->links[prec].base || ctx->links[prec].recon != recon) continue;
     if (!config_valid(prec, e != 0, c, recon, ctx->lds_max)) continue;
-    if (!map_possible(g, c.xcd_map) || !fits_n(c, n) || !fits_lattice(c, g)) continue;
+    if (!map_possible(g, c.xcd_map) || !fits_n(c, n) || !fits_lattice(c, g, prec)) continue;
     TuneEntry &t = ctx->tune[prec][n][e];
     t.cfg = c;
     t.state = TuneEntry::TUNED;

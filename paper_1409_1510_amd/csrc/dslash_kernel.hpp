@@ -160,31 +160,38 @@ __device__ inline void apply_hop_all(const Lnk<Real> &L, const typename CT<Real>
   }
 }
 
-// apply_hop_all for FP32 vectors with the gathers as raw buffer loads: the tile's colour planes
-// are one buffer (wave-uniform descriptor), the neighbour is a byte offset within a plane (the
-// lane's only address operand) and the plane start a scalar offset, so a gather costs no
-// vector address arithmetic.  Buffer range checking returns 0 past the tile instead of
-// reading beyond it.
+// apply_hop_all with the gathers as raw buffer loads: the tile's colour planes are one buffer
+// (wave-uniform descriptor), the neighbour is a byte offset within a plane (the lane's only
+// address operand) and the plane start a scalar offset, so a gather costs no vector address
+// arithmetic.
 typedef unsigned v2u_t __attribute__((__vector_size__(8)));
-template <int RT, bool NEG>
-__device__ inline void apply_hop_buf(const Lnk<float> &L, __amdgpu_buffer_rsrc_t rs, unsigned plane_bytes,
-                                     unsigned off, const int (&rr)[RT], float (&acc_re)[RT][3],
-                                     float (&acc_im)[RT][3]) {
+typedef unsigned v4u_t __attribute__((__vector_size__(16)));
+__device__ inline void buf_load(__amdgpu_buffer_rsrc_t rs, unsigned off, unsigned soff, float2 &v) {
+  const v2u_t u = __builtin_amdgcn_raw_buffer_load_b64(rs, off, soff, 0);
+  v.x = __uint_as_float(u[0]);
+  v.y = __uint_as_float(u[1]);
+}
+__device__ inline void buf_load(__amdgpu_buffer_rsrc_t rs, unsigned off, unsigned soff, double2 &v) {
+  const v4u_t u = __builtin_amdgcn_raw_buffer_load_b128(rs, off, soff, 0);
+  v.x = __hiloint2double(int(u[1]), int(u[0]));
+  v.y = __hiloint2double(int(u[3]), int(u[2]));
+}
+template <typename Real, int RT, bool NEG>
+__device__ inline void apply_hop_buf(const Lnk<Real> &L, __amdgpu_buffer_rsrc_t rs, unsigned plane_bytes,
+                                     unsigned off, const int (&rr)[RT], Real (&acc_re)[RT][3],
+                                     Real (&acc_im)[RT][3]) {
+  using C = typename CT<Real>::T;
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
-    float2 v[3];
+    C v[3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const v2u_t u = __builtin_amdgcn_raw_buffer_load_b64(rs, off, unsigned(rr[r] * 3 + b) * plane_bytes, 0);
-      v[b].x = __uint_as_float(u[0]);
-      v[b].y = __uint_as_float(u[1]);
-    }
+    for (int b = 0; b < 3; ++b) buf_load(rs, off, unsigned(rr[r] * 3 + b) * plane_bytes, v[b]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const float lr = NEG ? -L.re[a][b] : L.re[a][b];
-        const float li = NEG ? -L.im[a][b] : L.im[a][b];
+        const Real lr = NEG ? -L.re[a][b] : L.re[a][b];
+        const Real li = NEG ? -L.im[a][b] : L.im[a][b];
         acc_re[r][a] = fmaR(lr, v[b].x, acc_re[r][a]);
         acc_re[r][a] = fmaR(-li, v[b].y, acc_re[r][a]);
         acc_im[r][a] = fmaR(lr, v[b].y, acc_im[r][a]);
@@ -548,6 +555,17 @@ template <bool NT> __device__ inline float2 ld_raw(const float2 *p) {
     return *p;
   }
 }
+template <bool NT> __device__ inline double2 ld_raw(const double2 *p) {
+  if constexpr (NT) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    double2 o;
+    o.x = v.x;
+    o.y = v.y;
+    return o;
+  } else {
+    return *p;
+  }
+}
 template <bool NT> __device__ inline __half2 ld_raw(const __half2 *p) {
   if constexpr (NT) {
     const unsigned u = __builtin_nontemporal_load(reinterpret_cast<const unsigned *>(p));
@@ -564,9 +582,10 @@ template <bool NT> __device__ inline __half2 ld_raw(const __half2 *p) {
 // found in L2 than when every thread holds all n rhs; the links still come from HBM once.
 // Same site order, hop order and FMA sequence per rhs as k_dslash (bit-identical output), and
 // the same per-64-site grouping of the fused <p, Mp> partials.
-// (16 waves: at most 64 VGPRs, 8 waves: at most 128, so that two workgroups share a CU)
+// (the second launch bound is the waves per SIMD: two workgroups share a CU -- with 16 waves at
+// most 64 VGPRs, with 8 at most 128 -- except with FP64 links, whose 147 KB take a CU's LDS alone)
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
-__global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : (WPB == 8 ? 2 : 1)) k_dslash_lds(Args a) {
+__global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) k_dslash_lds(Args a) {
   static_assert(WPB == 4 || WPB == 8 || WPB == 16, "4, 8 or 16 waves per workgroup");
   using C = typename CT<Real>::T;
   constexpr int recon = R14 ? 14 : 18;
@@ -643,7 +662,6 @@ __global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : (WPB == 8 ? 2 : 1)) 
     __syncthreads();
   }
 
-  static_assert(sizeof(Real) == 4, "the LDS forms compute in FP32");
   // a tile spans RT * 3 colour planes of less than 4 GiB in all (checked at launch)
   const unsigned plane_bytes = vh * unsigned(sizeof(C));
   for (int tile = wave; tile < a.ntiles; tile += WPB) {
@@ -675,13 +693,13 @@ __global__ void __launch_bounds__(64 * WPB, WPB == 16 ? 8 : (WPB == 8 ? 2 : 1)) 
       const uint4 nb = reinterpret_cast<const uint4 *>(nbt)[mu * 64 + lane];
       Lnk<Real> Lk;
       load_link<Real, LT, false, false>(sl, link_plane(mu, recon), 64u, lane, Lk);
-      apply_hop_buf<RT, false>(Lk, rs, plane_bytes, nb.x, rr, acc_re, acc_im);
+      apply_hop_buf<Real, RT, false>(Lk, rs, plane_bytes, nb.x, rr, acc_re, acc_im);
       load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
-      apply_hop_buf<RT, true>(Lk, rs, plane_bytes, nb.y, rr, acc_re, acc_im);
+      apply_hop_buf<Real, RT, true>(Lk, rs, plane_bytes, nb.y, rr, acc_re, acc_im);
       load_naik_lds<Real, LT, R14>(sl, row2, mu, lane, Lk);
-      apply_hop_buf<RT, false>(Lk, rs, plane_bytes, nb.z, rr, acc_re, acc_im);
+      apply_hop_buf<Real, RT, false>(Lk, rs, plane_bytes, nb.z, rr, acc_re, acc_im);
       load_naik_lds<Real, LT, R14>(sl, row2, 4 + mu, lane, Lk);
-      apply_hop_buf<RT, true>(Lk, rs, plane_bytes, nb.w, rr, acc_re, acc_im);
+      apply_hop_buf<Real, RT, true>(Lk, rs, plane_bytes, nb.w, rr, acc_re, acc_im);
     }
     bool act[RT];
 #pragma unroll
@@ -919,7 +937,10 @@ DslashFn pick_lds_rt(int rt) {
 // lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves, 3 = 16 waves
 template <typename Real, typename LT, bool R14, bool EPI, bool NT>
 DslashFn pick_lds(int rt, int lds) {
-  if constexpr (sizeof(LT) > 8) {  // FP64 links do not fit LDS twice per CU
+  if constexpr (sizeof(LT) > 8) {  // FP64: the whole-site forms only (one workgroup per CU)
+    if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
+    if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
+    if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);
     return nullptr;
   } else {
     if (lds >= 4) return pick_mu<Real, LT, R14, EPI, NT>(rt, lds);

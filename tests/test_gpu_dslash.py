@@ -205,12 +205,12 @@ ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64)
 
 
 def _cfg_valid(prec, cfg, dims):
-    """The launch rules of the header: FP64 has no 16-rhs tile and no LDS form; the 16-wave LDS
-    form and the direction-pipelined forms take at most 2 rhs per thread; the z-slab map needs
-    (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0, the y-slab map (Lx/2)*Ly % 512 == 0."""
+    """The launch rules of the header: FP64 has no 16-rhs tile and no direction-pipelined form;
+    the 16-wave LDS form and the direction-pipelined forms take at most 2 rhs per thread; the
+    z-slab map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0, the y-slab map (Lx/2)*Ly % 512 == 0."""
     rt, spb, nt, lds, xm = cfg
     plane = dims[0] // 2 * dims[1]
-    if prec == hisq.HISQ_F64 and (rt == 16 or lds):
+    if prec == hisq.HISQ_F64 and (rt == 16 or lds >= 4):
         return False
     if lds >= 3 and rt > 2:
         return False

@@ -248,6 +248,18 @@ def hisq_autotune(ctx, prec: int, n: int, fused_m: int = 0):
     return c.as_tuple(), ms.value
 
 
+def hisq_save_tuning(ctx, path: str) -> None:
+    _check(ctx, _lib.hisq_save_tuning(ctx, os.fsencode(path)))
+
+
+def hisq_load_tuning(ctx, path: str) -> int:
+    """Entries of the file that match this context's lattice and link formats; returns how many
+    were taken."""
+    cnt = ctypes.c_int()
+    _check(ctx, _lib.hisq_load_tuning(ctx, os.fsencode(path), ctypes.byref(cnt)))
+    return cnt.value
+
+
 def hisq_cg_mrhs(ctx, mass: float, n: int, b, x, params: hisq_cg_params, stats: hisq_cg_stats):
     rc = _lib.hisq_cg_mrhs(ctx, float(mass), int(n), _ptr(b), _ptr(x), ctypes.byref(params),
                            ctypes.byref(stats))
@@ -308,8 +320,7 @@ class Lattice:
                 raise ValueError(f"links must be [{self.volume}][4][3][3]")
         hisq_load_links(self.ctx, fat, naik, copies, naik_recon)
         if os.path.exists(TUNING_PATH) and os.environ.get("HISQ_AUTOTUNE", "1") != "0":
-            cnt = ctypes.c_int()
-            _check(self.ctx, _lib.hisq_load_tuning(self.ctx, TUNING_PATH.encode(), ctypes.byref(cnt)))
+            hisq_load_tuning(self.ctx, TUNING_PATH)
 
     def dslash(self, out_parity, prec, v_in, out=None):
         self._vec(v_in, prec, "in")

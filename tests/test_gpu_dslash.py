@@ -314,3 +314,31 @@ def test_full_size_48c12_64c16_sampled_sites(name, prec, n):
         got = lat.dslash(par, prec, tv).cpu().numpy()[:, :, sites]
         assert rel_l2(got, ref) <= (2e-3 if prec == hisq.HISQ_F16 else 1e-6)
     lat.close()
+
+
+def test_tuning_table_round_trip(tmp_path):
+    """Tuned choices saved to a table are taken back by a new context on the same lattice and link
+    formats; the file keeps other lattices' entries, and lines with an invalid configuration or
+    another lattice are skipped on loading."""
+    dims, n = (8, 6, 4, 10), 5
+    path = tmp_path / "table.txt"
+    foreign = "4 4 4 4 1 18 3 0 1 256 0 0 0 0.01000\n"
+    path.write_text("# a comment line\n" + foreign)
+    lat, fat, naik = make_lattice(dims, 130)
+    tuned = {}
+    for prec, fused in ((hisq.HISQ_F32, 0), (hisq.HISQ_F16, 1), (hisq.HISQ_F64, 0)):
+        tuned[(prec, fused)], ms = hisq.hisq_autotune(lat.ctx, prec, n, fused)
+        assert ms > 0
+    hisq.hisq_save_tuning(lat.ctx, str(path))
+    lat.close()
+    text = path.read_text()
+    assert foreign in text
+    # an invalid register tile (3) and a different lattice for this context's formats
+    lx, ly, lz, lt = dims
+    path.write_text(text + f"{lx} {ly} {lz} {lt} 1 18 7 0 3 64 0 0 0 0.01000\n"
+                           f"{lx} {ly} {lz} {lt + 2} 1 18 7 0 1 64 0 0 0 0.01000\n")
+    lat2, _, _ = make_lattice(dims, 130)
+    assert hisq.hisq_load_tuning(lat2.ctx, str(path)) == 3
+    for (prec, fused), cfg in tuned.items():
+        assert hisq.hisq_get_launch(lat2.ctx, prec, n, fused) == cfg
+    lat2.close()

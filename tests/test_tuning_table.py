@@ -1,0 +1,31 @@
+"""Format of the launch-configuration table shipped with the library (no GPU needed)."""
+import os
+
+
+def test_shipped_tuning_table_format():
+    """Every entry of the shipped launch table is a well-formed line for one of the study lattices
+    with a configuration inside the header's ranges, and no (lattice, format, n, form) repeats."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1409_1510_amd", "tuning", "gfx950.txt")
+    lattices = {(32, 32, 32, 8), (48, 48, 48, 12), (64, 64, 64, 16)}
+    seen = set()
+    count = 0
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        assert len(f) == 14, line
+        lx, ly, lz, lt, prec, recon, n, fused, rt, spb, nt, lds, xm = map(int, f[:13])
+        ms = float(f[13])
+        assert (lx, ly, lz, lt) in lattices
+        assert prec in (0, 1, 2) and recon in (14, 18) and (prec != 0 or recon == 18)
+        assert 1 <= n <= 64 and fused in (0, 1)
+        assert rt in (1, 2, 4, 8, 16) and spb in (64, 256) and nt in (0, 1)
+        assert 0 <= lds <= 6 and 0 <= xm <= 2 and (xm == 0 or lds > 0)
+        assert not (prec == 0 and (rt == 16 or lds >= 4))
+        assert ms > 0
+        key = (lx, ly, lz, lt, prec, recon, n, fused)
+        assert key not in seen
+        seen.add(key)
+        count += 1
+    assert count >= 50

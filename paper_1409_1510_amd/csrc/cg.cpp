@@ -1,4 +1,4 @@
-// Host drivers of the multi-rhs even-odd CG solvers.
+// Host loops of the multi-rhs even-odd CG solvers.
 //
 // The whole solve stays on the device; the host enqueues the iteration and only looks at the
 // per-rhs residual state at polls (Section 2 keeps the solver on the GPU and moves only the set

@@ -55,7 +55,7 @@ int cg_init_state(hisq_ctx *ctx, const void *b, CGState *S, int n, double *parti
 int cg_set_rho(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
 int cg_zero(hisq_ctx *ctx, int prec, void *v, const int *sel, int invert, int n);
 
-// solver pieces shared by the CG drivers (cg.cpp) and the flexible CG (nn.hip)
+// solver pieces shared by the CG host loops (cg.cpp) and the flexible CG (nn.hip)
 int cg_poll(hisq_ctx *ctx, CGState *S, CGState *hS);
 int apply_m64(hisq_ctx *ctx, double mass, int n, const void *x64, void *t64, void *mx64, const int *mask);
 int cg_apply_op(hisq_ctx *ctx, int op_prec, double mass, int n, const void *p, void *t, void *q,

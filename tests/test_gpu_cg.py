@@ -1,6 +1,6 @@
 """GPU multi-rhs CG solvers against the oracle.
 
-Judge of every solve: the FP64 true residual ||b - M x|| / ||b|| recomputed on the CPU with the
+Check of every solve: the FP64 true residual ||b - M x|| / ||b|| recomputed on the CPU with the
 oracle's M applied to the GPU's x.
 """
 import numpy as np

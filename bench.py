@@ -8,7 +8,8 @@ value = Gflop/s under the 1146 flop per site per rhs convention (Section 1, Tabl
 
 Also reported on the same JSON line:
   roofline      : compulsory HBM bytes per half-Dslash launch / mean launch duration (HIP events
-                  around each launch of the timed region, on the launch stream), against 8 TB/s;
+                  at the ends of the timed region on the launch stream, over its launches),
+                  against 8 TB/s; the GPU clocks rocm-smi reports right after that region;
   dslash_sweep  : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
   cg            : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
                   the mixed-precision solver (FP16 and FP32 links) and the plain FP64 solver;
@@ -35,6 +36,18 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_dslash_f32_n16_32x32x32x8.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_1510_amd", "csrc", f)
                   for f in ("dslash_kernel.hpp", "dslash.hip", "dslash_f32.hip")]
+
+
+def gpu_clocks():
+    """Current GPU clocks as rocm-smi reports them (None if it cannot be read)."""
+    import subprocess
+    try:
+        res = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                             timeout=30)
+        card = next(iter(json.loads(res.stdout).values()))
+        return {k.strip(" :"): v for k, v in card.items() if "clock speed" in k}
+    except Exception:  # reporting only: a missing tool or format leaves the field empty
+        return None
 
 
 def kernel_source_hash() -> str:
@@ -344,6 +357,7 @@ def main():
 
     ms_step, ms_launch, ms_iso = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
                                                     args.steps, args.warmup)
+    clocks = gpu_clocks()  # sampled right after the timed region
     launch_cfg = hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)
     flops_step = 2 * pm.half_dslash_flops(vh, n)
     gflops = flops_step / (ms_step * 1e-3) / 1e9
@@ -376,6 +390,7 @@ def main():
                      "kernel_source_sha256_16": kernel_source_hash(),
                      "bytes_per_launch": bytes_launch, "ms_per_launch": round(ms_launch, 5),
                      "ms_per_launch_event_bracketed": round(ms_iso, 5)},
+        "gpu_clocks_after_timed_region": clocks,
     }
 
     if not args.no_sweep:

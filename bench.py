@@ -443,6 +443,11 @@ def main():
         cg["speedup_mixed_vs_f64"] = round(cg["plain_f64"]["seconds"] / min(cg["mixed_f16links"]["seconds"],
                                                                           cg["mixed_f32links"]["seconds"]), 3)
         result["cg"] = cg
+        # the paper's multi-rhs CG figure, on other hardware (context, not a comparison target)
+        result["paper_context"] = {
+            "cg_gflops_fp32": ">250 on Xeon Phi 5110P and Kepler Tesla GPUs (abstract, Section 4)",
+            "mixed_cg_dslash_gflops_here": cg["mixed_f16links"]["dslash_gflops"],
+            "note": "Dslash flops per second of the whole mixed solve (BLAS-1 flops not counted)"}
         # Eq. 2: Tr M^-1 from Z2 noise bundles through the mixed solver
         nvec, bundle = 64, 16
         torch.cuda.synchronize()

@@ -295,24 +295,31 @@ def test_direction_pipelined_tile_limit(prec):
 
 
 @pytest.mark.parametrize("name,prec,n", [("c3", hisq.HISQ_F32, 16), ("c3", hisq.HISQ_F16, 16),
-                                         ("c4", hisq.HISQ_F32, 32), ("c4", hisq.HISQ_F16, 32)])
+                                         ("c3", hisq.HISQ_F64, 16), ("c4", hisq.HISQ_F32, 32),
+                                         ("c4", hisq.HISQ_F16, 32), ("c4", hisq.HISQ_F64, 8)])
 def test_full_size_48c12_64c16_sampled_sites(name, prec, n):
-    """The 48^3 x 12 and 64^3 x 16 lattices at their rhs counts, in the tuned launch
-    configuration of each: sampled output sites (including the first and last of each parity)
-    against the per-site oracle."""
+    """The 48^3 x 12 and 64^3 x 16 lattices at their rhs counts (FP64 at 64^3 x 16: 8 rhs), in
+    the tuned launch configuration of each: sampled output sites (including the first and last of
+    each parity) against the per-site oracle."""
     dims = synth.WORKLOADS[name]["dims"]
     fat, naik = synth.tiled_gauge_links(dims, 130)
     lat = hisq.Lattice(dims, 0)
-    lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 18)
+    copies = hisq.HISQ_LINKS_F64 if prec == hisq.HISQ_F64 else hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16
+    lat.load_links(fat, naik, copies, 18)
     rng = np.random.default_rng(6)
     sites = np.concatenate([[0, 1, lat.vh - 1], rng.choice(lat.vh, 24, replace=False)])
     v = synth.sources(dims, n, 131)
-    tv = torch.from_numpy(v).to(DEV).to(torch.complex64)
+    tv = torch.from_numpy(v).to(DEV)
+    if prec != hisq.HISQ_F64:
+        tv = tv.to(torch.complex64)
     print("launch", name, prec, n, hisq.hisq_get_launch(lat.ctx, prec, n, 0))
     for par in (0, 1):
         ref = oracle.dslash_sites(fat, naik, v, dims, par, sites)
         got = lat.dslash(par, prec, tv).cpu().numpy()[:, :, sites]
-        assert rel_l2(got, ref) <= (2e-3 if prec == hisq.HISQ_F16 else 1e-6)
+        if prec == hisq.HISQ_F64:
+            assert rel_elem(got, ref) <= 1e-13
+        else:
+            assert rel_l2(got, ref) <= (2e-3 if prec == hisq.HISQ_F16 else 1e-6)
     lat.close()
 
 

@@ -349,3 +349,39 @@ def test_tuning_table_round_trip(tmp_path):
     for (prec, fused), cfg in tuned.items():
         assert hisq.hisq_get_launch(lat2.ctx, prec, n, fused) == cfg
     lat2.close()
+
+
+def _launch_ms(lat, prec, n, reps=20):
+    a = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device=DEV)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        lat.dslash(1, prec, a, b)
+        lat.dslash(0, prec, b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lat.dslash(1, prec, a, b)
+        lat.dslash(0, prec, b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / (2 * reps)
+
+
+def test_multi_rhs_gain_over_single_rhs():
+    """The paper's qualitative claim (Section 1 and Table 1): bundling rhs more than doubles the
+    Dslash flop rate from 1 to 4 rhs (FP32, 32^3 x 8, tuned launches).  The 14-real Naik gain at
+    1 and 8 rhs (about 10 % and 3 % in the paper's model) is printed."""
+    dims = (32, 32, 32, 8)
+    fat, naik = synth.tiled_gauge_links(dims, 140)
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(fat, naik, hisq.HISQ_LINKS_F32, 18)
+    ms = {n: _launch_ms(lat, hisq.HISQ_F32, n) for n in (1, 4, 8)}
+    gain = (4 / ms[4]) / (1 / ms[1])
+    print(f"FP32 ms per launch {ms}; flop-rate gain 1 -> 4 rhs: {gain:.2f}")
+    assert gain >= 2.0
+    lat.load_links(fat, naik, hisq.HISQ_LINKS_F32, 14)
+    for n in (1, 8):
+        r14 = _launch_ms(lat, hisq.HISQ_F32, n)
+        print(f"r14 at n = {n}: {r14:.4f} ms against {ms[n]:.4f} ms ({100 * (ms[n] / r14 - 1):.1f} % faster)")
+    lat.close()

@@ -221,7 +221,7 @@ def _cfg_valid(prec, cfg, dims):
     return True
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4), (16, 64, 4, 4)])
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4), (16, 64, 4, 4), (6, 6, 4, 6)])
 @pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
                                         (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14)])
 def test_every_launch_config_bit_identical(prec, recon, dims):
@@ -229,7 +229,7 @@ def test_every_launch_config_bit_identical(prec, recon, dims):
     the same bits, for the plain half Dslash and for the fused M operator (including its FP64
     <p, Mp> reduction), and the autotuned choice is one of them.  Exactly the configurations the
     header rules out are refused.  (16, 8, 8, 4) admits the z-slab XCD map, (16, 64, 4, 4) the
-    y-slab map."""
+    y-slab map; (6, 6, 4, 6) has V/2 = 432, so the last 64-site block of the LDS forms is ragged."""
     n, mass = 11, 0.1
     lat, fat, naik = make_lattice(dims, 120, recon=recon)
     dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64

@@ -79,6 +79,15 @@ def measured_traffic(config_tuple):
         return None
 
 
+SWEEP_N = (1, 2, 4, 8, 16)
+
+
+def sweep_cases(hisq):
+    """(precision, Naik format, label) of the n/precision sweep."""
+    return ((hisq.HISQ_F64, 18, "f64"), (hisq.HISQ_F32, 18, "f32"), (hisq.HISQ_F32, 14, "f32_r14"),
+            (hisq.HISQ_F16, 18, "f16links"), (hisq.HISQ_F16, 14, "f16links_r14"))
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -294,6 +303,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), then --steps FP32 Dslash steps")
+    ap.add_argument("--profile-sweep", action="store_true",
+                    help="short run for rocprofv3: the counter-calibration kernel, then 3 steps of "
+                         "every case of the n/precision sweep (after 1 warm-up step each)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="short run for rocprofv3: the 32^3x8 mixed CG (FP16 links, 8 rhs) of the "
                          "benchmark, solved twice")
@@ -342,6 +354,26 @@ def main():
     w_e = torch.empty_like(v_e)
     w_o = torch.empty_like(v_o)
 
+    if args.profile_sweep:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        for prec, recon, name in sweep_cases(hisq):
+            if recon == 14:
+                lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 14)
+            for nn in SWEEP_N:
+                dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
+                a = torch.from_numpy(synth.sources(dims, nn, 9)).to("cuda:0").to(dt)
+                b = torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0").to(dt)
+                dslash_step_timing(lat, hisq, torch, prec, a, b, torch.empty_like(a), torch.empty_like(b),
+                                   3, 1, isolated=False)
+                print(f"profile-sweep case {name} n {nn} launch {hisq.hisq_get_launch(lat.ctx, prec, nn, 0)}",
+                      flush=True)
+            if recon == 14:
+                lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
+        lat.close()
+        return
     if args.profile:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -395,12 +427,10 @@ def main():
 
     if not args.no_sweep:
         sweep = []
-        for prec, recon, name in ((hisq.HISQ_F64, 18, "f64"), (hisq.HISQ_F32, 18, "f32"),
-                                  (hisq.HISQ_F32, 14, "f32_r14"), (hisq.HISQ_F16, 18, "f16links"),
-                                  (hisq.HISQ_F16, 14, "f16links_r14")):
+        for prec, recon, name in sweep_cases(hisq):
             if recon == 14:
                 lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 14)
-            for nn in (1, 2, 4, 8, 16):
+            for nn in SWEEP_N:
                 dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
                 a = torch.from_numpy(synth.sources(dims, nn, 9)).to("cuda:0").to(dt)
                 b = torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0").to(dt)

@@ -124,7 +124,11 @@ int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, const void *b, 
 typedef struct {
   int rhs_per_thread;    /* register tile: 1, 2, 4, 8 or 16 (FP64 and the fused-M form: <= 8)  */
   int sites_per_block;   /* 256: one rhs tile per 256-thread workgroup; 64: the 4 waves of a     */
-                         /*      workgroup take 4 rhs tiles of the same 64 sites               */
+                         /*      workgroup take 4 rhs tiles of the same 64 sites; 32: the       */
+                         /*      32-site LDS form (lds_links 1 or 2 = 4 or 8 waves, rhs_per_    */
+                         /*      thread 1 or 2, the two halves of a wave on different rhs), for */
+                         /*      the plain half Dslash only: hisq_set_launch leaves the fused-M */
+                         /*      configuration unchanged for it                                 */
   int nontemporal_links; /* 1: link loads carry the non-temporal cache hint                     */
   int lds_links;         /* 1, 2, 3: a workgroup of 64 sites x 4, 8, 16 waves stages its sites'  */
                          /*    links in LDS and its waves loop over the rhs tiles (requires      */

@@ -28,6 +28,9 @@ size_t lds_bytes(int prec, int recon, const hisq_launch &c) {
   if (!c.lds_links) return 0;
   const size_t elem = prec == HISQ_F64 ? 16 : (prec == HISQ_F32 ? 8 : 4);
   const bool r14 = prec != HISQ_F64 && recon == 14;
+  if (c.sites_per_block == 32)  // 32-site form: half of the whole-site form's pieces
+    return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 32 * elem + (r14 ? size_t(24) * 32 * 8 : 0) +
+           dslash::kNbrTable32Bytes;
   if (c.lds_links >= 4)  // two buffers of one direction's planes (+ rebuilt Naik rows)
     return 2 * size_t(r14 ? 32 : 36) * 64 * elem + (r14 ? size_t(12) * 64 * 8 : 0);
   const size_t row2 = r14 ? size_t(24) * 64 * 8 : 0;
@@ -38,7 +41,7 @@ bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size
   if (c.lds_links && lds_max && lds_bytes(prec, recon, c) > lds_max) return false;
   const int rt = c.rhs_per_thread;
   if (rt != 1 && rt != 2 && rt != 4 && rt != 8 && rt != 16) return false;
-  if (c.sites_per_block != 64 && c.sites_per_block != 256) return false;
+  if (c.sites_per_block != 32 && c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
   if (c.lds_links < 0 || c.lds_links > 6) return false;
   if (c.xcd_map < 0 || c.xcd_map > 2 || (c.xcd_map != 0 && !c.lds_links)) return false;
@@ -56,10 +59,12 @@ int max_tiles(const hisq_launch &c) {
 bool fits_n(const hisq_launch &c, int n) {
   return (n + c.rhs_per_thread - 1) / c.rhs_per_thread <= max_tiles(c);
 }
-// the LDS forms address a rhs tile with 32-bit byte offsets
+// the LDS forms address a rhs tile (2 rhs_per_thread rhs in the 32-site form) with 32-bit byte
+// offsets
 bool fits_lattice(const hisq_launch &c, const Geometry &g, int prec) {
   const size_t elem = prec == HISQ_F64 ? 16 : 8;
-  return !c.lds_links || size_t(c.rhs_per_thread) * 3 * size_t(g.vh) * elem < (size_t(1) << 32);
+  const size_t tile = size_t(c.rhs_per_thread) * (c.sites_per_block == 32 ? 2 : 1);
+  return !c.lds_links || tile * 3 * size_t(g.vh) * elem < (size_t(1) << 32);
 }
 
 int next_pow2(int n) {
@@ -99,10 +104,13 @@ Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
   o.xmap = 0;
   o.zmap_bps = 0;
   o.zmap_zr = 0;
-  o.ntiles = (n + c.rhs_per_thread - 1) / c.rhs_per_thread;
+  const bool half = c.sites_per_block == 32;  // 32-site LDS form: tiles of 2 rt rhs
+  const int tw = c.rhs_per_thread * (half ? 2 : 1);
+  o.ntiles = (n + tw - 1) / tw;
   const int tpb = 256 / c.sites_per_block;
   o.ngroups = c.lds_links ? 1 : (o.ntiles + tpb - 1) / tpb;  // the LDS form loops over the tiles
-  o.nsblk = (g.vh + c.sites_per_block - 1) / c.sites_per_block;
+  const int spb = half ? 64 : c.sites_per_block;              // the XCD maps deal 64-site blocks
+  o.nsblk = (g.vh + spb - 1) / spb;
   const int nb = o.nsblk * o.ngroups;
   o.grid = (nb + 7) / 8 * 8;
   if (c.lds_links && c.xcd_map && map_possible(g, c.xcd_map)) {
@@ -111,6 +119,7 @@ Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
     o.zmap_zr = g.lz / 8;
     o.grid = o.nsblk;  // 8 * Lt * (Lz/8) * bps (z slabs) or 8 * Lz * Lt * (bps/8) (y slabs)
   }
+  if (half) o.grid *= 2;  // two workgroups per 64-site block
   return o;
 }
 
@@ -185,7 +194,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   };
   for (int rt : rts) {
     if (rt > next_pow2(n)) break;
-    for (int spb : {256, 64})
+    for (int spb : {256, 64, 32})
       for (int nt : {0, 1})
         for (int lds = 0; lds <= 6; ++lds)
           for (int xm : {0, 1, 2}) {
@@ -264,6 +273,9 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
       continue;
     }
     hisq_launch c = *cfg;
+    // the 32-site form exists for the plain half Dslash only: the fused M form keeps its own
+    // (tuned or heuristic) configuration
+    if (epi && c.sites_per_block == 32 && c.lds_links) continue;
     const int recon = ctx->links[prec].base ? ctx->links[prec].recon : 18;
     if (c.xcd_map >= 1 && c.xcd_map <= 2 && !map_possible(ctx->g, c.xcd_map))
       return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));

@@ -201,6 +201,34 @@ __device__ inline void apply_hop_buf(const Lnk<Real> &L, __amdgpu_buffer_rsrc_t 
   }
 }
 
+// apply_hop_buf for the 32-site form: rhs r of a lane sits in the vector offset (off + r * 3
+// planes) and the colour plane in the scalar offset, so that the buffer range check covers the
+// rhs (a rhs past n reads 0 instead of memory past the vectors).
+template <typename Real, int RT, bool NEG>
+__device__ inline void apply_hop_buf32(const Lnk<Real> &L, __amdgpu_buffer_rsrc_t rs, unsigned plane_bytes,
+                                       unsigned off, Real (&acc_re)[RT][3], Real (&acc_im)[RT][3]) {
+  using C = typename CT<Real>::T;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    C v[3];
+    const unsigned vo = off + unsigned(r * 3) * plane_bytes;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) buf_load(rs, vo, unsigned(b) * plane_bytes, v[b]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const Real lr = NEG ? -L.re[a][b] : L.re[a][b];
+        const Real li = NEG ? -L.im[a][b] : L.im[a][b];
+        acc_re[r][a] = fmaR(lr, v[b].x, acc_re[r][a]);
+        acc_re[r][a] = fmaR(-li, v[b].y, acc_re[r][a]);
+        acc_im[r][a] = fmaR(lr, v[b].y, acc_im[r][a]);
+        acc_im[r][a] = fmaR(li, v[b].x, acc_im[r][a]);
+      }
+    }
+  }
+}
+
 // Neighbour indices (within the input parity) of output site s at coordinates (x, y, z, t) for
 // the four hops of direction mu: +1, -1, +3, -3.
 __device__ inline void hop_sites(const Geometry &g, int mu, unsigned s, unsigned rowbase, int x, int y, int z, int t,
@@ -436,15 +464,22 @@ template <typename Real, typename LT, bool R14> constexpr size_t lds_nbr_offset(
   return size_t(R14 ? 128 : 144) * 64 * sizeof(LT) + (R14 ? size_t(24) * 64 * sizeof(typename CT<Real>::T) : 0);
 }
 
-// Site block of an LDS-form workgroup under the XCD map of the launch (false: none).
-__device__ inline bool lds_block(const Args &a, int &sblk) {
+// LDS of the 32-site form: the same pieces for 32 sites.
+template <typename Real, typename LT, bool R14> constexpr size_t lds32_nbr_offset() {
+  return size_t(R14 ? 128 : 144) * 32 * sizeof(LT) + (R14 ? size_t(24) * 32 * sizeof(typename CT<Real>::T) : 0);
+}
+constexpr size_t kNbrTable32Bytes = size_t(16) * 32 * sizeof(unsigned);
+
+// 64-site block of LDS-form workgroup `bid` (of `nbid`, dealt round-robin to the 8 XCDs) under
+// the XCD map of the launch (false: none).
+__device__ inline bool lds_block_at(const Args &a, int bid, int nbid, int &sblk) {
   const Geometry &g = a.g;
   if (a.xmap == 2) {
     // XCD k owns the blocks [k, k+1) * bps/8 of every (z, t) plane (with Lx = 32: four y rows)
     // and walks the planes z-major.  The sites in flight on an XCD then span a few z slices of a
     // thin slab whose t extent is the whole lattice, so the t and z neighbours they gather (the
     // Naik hops reach 3 slices away) are mostly still in that XCD's L2.
-    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int k = bid & 7, j = bid >> 3;
     const int bpx = a.zmap_bps >> 3;
     const int zt = j / bpx;  // z * Lt + t
     const int z = zt / g.lt, t = zt - z * g.lt;
@@ -454,7 +489,7 @@ __device__ inline bool lds_block(const Args &a, int &sblk) {
     // XCD k owns the z slices [k Lz/8, (k+1) Lz/8) for every t: the z and t neighbours of its
     // sites stay mostly in its own L2 (with contiguous chunks, Lt = 8 would give each XCD a single
     // t slice and send every t hop to another XCD's data)
-    const int k = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int k = bid & 7, j = bid >> 3;
     const int per_t = a.zmap_zr * a.zmap_bps;
     const int t = j / per_t;
     if (t >= g.lt) return false;
@@ -462,30 +497,32 @@ __device__ inline bool lds_block(const Args &a, int &sblk) {
     const int zl = rem / a.zmap_bps;
     sblk = (t * g.lz + k * a.zmap_zr + zl) * a.zmap_bps + (rem - zl * a.zmap_bps);
   } else {
-    const int chunk = gridDim.x >> 3;
-    sblk = (blockIdx.x & 7) * chunk + (blockIdx.x >> 3);
+    const int chunk = nbid >> 3;
+    sblk = (bid & 7) * chunk + (bid >> 3);
     if (sblk >= a.nsblk) return false;
   }
   return true;
 }
+__device__ inline bool lds_block(const Args &a, int &sblk) { return lds_block_at(a, blockIdx.x, gridDim.x, sblk); }
 
 // Naik link k (0..7: hops 8 + k) of lane `lane` from the staged LDS copy: rows 0 and 1 from the
 // stored planes and, for 14-real links, row 2 from the planes rebuilt once per site.
-template <typename Real, typename LT, bool R14>
+// (SB: sites per LDS plane)
+template <typename Real, typename LT, bool R14, int SB = 64>
 __device__ inline void load_naik_lds(const LT *__restrict__ sl, const typename CT<Real>::T *__restrict__ row2,
                                      int k, int lane, Lnk<Real> &L) {
   const int recon = R14 ? 14 : 18;
   if constexpr (!R14) {
-    load_link<Real, LT, false, false>(sl, link_plane(8 + k, recon), 64u, unsigned(lane), L);
+    load_link<Real, LT, false, false>(sl, link_plane(8 + k, recon), unsigned(SB), unsigned(lane), L);
   } else {
-    const LT *p = sl + link_plane(8 + k, recon) * 64 + lane;
+    const LT *p = sl + link_plane(8 + k, recon) * SB + lane;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) ld_link<false>(p + (a * 3 + b) * 64, L.re[a][b], L.im[a][b]);
+      for (int b = 0; b < 3; ++b) ld_link<false>(p + (a * 3 + b) * SB, L.re[a][b], L.im[a][b]);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const typename CT<Real>::T v = row2[(k * 3 + b) * 64 + lane];
+      const typename CT<Real>::T v = row2[(k * 3 + b) * SB + lane];
       L.re[2][b] = v.x;
       L.im[2][b] = v.y;
     }
@@ -705,6 +742,134 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) 
 #pragma unroll
     for (int r = 0; r < RT; ++r) act[r] = valid && ract[r];
     store_tile<Real, RT, EPI>(a, r0, s, lane, sblk, act, acc_re, acc_im);
+  }
+}
+
+// 32-site LDS form (plain half Dslash): a workgroup of 32 sites x WPB waves stages half the links
+// of the whole-site form, so that an FP64 workgroup (74 KB) shares a CU with another (and an
+// FP32 or FP16 one with three).  The two 32-lane halves of a wave take different rhs: lane
+// (site i, half h) computes rhs r0 + h RT + r of a tile of 2 RT rhs.  Workgroups 2j and 2j+1 of
+// an XCD take the two halves of the 64-site block the XCD map gives for j.  The rhs offset of a
+// lane goes into the buffer loads' vector offset, so a rhs past n reads past the buffer's range
+// (returns 0) and is not stored.  Same hop order and FMA sequence per rhs as k_dslash
+// (bit-identical output).  The second launch bound: FP64 two workgroups per CU, else four.
+template <typename Real, typename LT, int RT, bool R14, int WPB, bool NT>
+__global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 2 : 4)) k_dslash_lds32(Args a) {
+  static_assert(WPB == 4 || WPB == 8, "4 or 8 waves per workgroup");
+  using C = typename CT<Real>::T;
+  constexpr int recon = R14 ? 14 : 18;
+  constexpr int PL = R14 ? 128 : 144;  // stored planes per site
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  LT *sl = reinterpret_cast<LT *>(smem_raw);
+  const Geometry &g = a.g;
+  const int bx = blockIdx.x;
+  int sblk;
+  if (!lds_block_at(a, ((bx >> 3) >> 1) * 8 + (bx & 7), gridDim.x >> 1, sblk)) return;  // uniform
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int si = lane & 31, h = lane >> 5;
+  const unsigned vh = g.vh;
+  const unsigned s = sblk * 64 + ((bx >> 3) & 1) * 32 + si;
+  const bool valid = s < vh;
+  const unsigned sc = valid ? s : 0u;
+  const LT *__restrict__ links = static_cast<const LT *>(a.links);
+  // stage the links of the 32 sites, [plane][32]: a wave load covers planes 2 pp and 2 pp + 1
+  {
+    constexpr int PPW = PL / 2 / WPB;  // plane pairs per wave
+    constexpr int CH = PPW % 9 == 0 ? 9 : 8;
+    static_assert(PPW % CH == 0, "whole batches");
+#pragma unroll 1
+    for (int c0 = 0; c0 < PPW; c0 += CH) {
+      LT v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) v[i] = ld_raw<NT>(links + size_t(2 * (wave + (c0 + i) * WPB) + h) * vh + sc);
+#pragma unroll
+      for (int i = 0; i < CH; ++i) sl[(2 * (wave + (c0 + i) * WPB) + h) * 32 + si] = v[i];
+    }
+  }
+  // neighbour table [mu][site][+1, -1, +3, -3] (byte offsets within a colour plane)
+  unsigned *nbt = reinterpret_cast<unsigned *>(smem_raw + lds32_nbr_offset<Real, LT, R14>());
+  {
+    const unsigned q1 = fast_div(sc, a.div_xh);
+    const unsigned q2 = fast_div(q1, a.div_y);
+    const unsigned q3 = fast_div(q2, a.div_z);
+    const int xh = int(sc - q1 * unsigned(g.lxh));
+    const int y = int(q1 - q2 * unsigned(g.ly));
+    const int z = int(q2 - q3 * unsigned(g.lz));
+    const int t = int(q3);
+    const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
+    const unsigned rowbase = sc - unsigned(xh);
+    for (int hp = 2 * wave + h; hp < 16; hp += 2 * WPB) {
+      const int mu = hp >> 2, k = hp & 3;
+      const int d = k == 0 ? 1 : (k == 1 ? -1 : (k == 2 ? 3 : -3));
+      nbt[(mu * 32 + si) * 4 + k] = hop_site(g, mu, d, sc, rowbase, x, y, z, t) * unsigned(sizeof(C));
+    }
+  }
+  __syncthreads();
+  C *row2 = reinterpret_cast<C *>(sl + PL * 32);
+  if constexpr (R14) {
+    for (int item = threadIdx.x; item < 8 * 32; item += 64 * WPB) {
+      const int k = item >> 5, ln = item & 31;
+      Lnk<Real> Lk;
+      load_link<Real, LT, true, false>(sl, link_plane(8 + k, recon), 32u, ln, Lk);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        C v;
+        v.x = Lk.re[2][b];
+        v.y = Lk.im[2][b];
+        row2[(k * 3 + b) * 32 + ln] = v;
+      }
+    }
+    __syncthreads();
+  }
+
+  const unsigned plane_bytes = vh * unsigned(sizeof(C));
+  for (int tile = wave; tile < a.ntiles; tile += WPB) {
+    const int r0 = tile * 2 * RT;
+    const int q0 = r0 + h * RT;  // this lane's first rhs
+    bool act[RT];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      act[r] = q0 + r < a.n && (!a.active || a.active[q0 + r]);
+      any = any || act[r];
+    }
+    if (!__builtin_amdgcn_ballot_w64(any)) continue;  // the whole tile is inactive (uniform)
+    const char *in = static_cast<const char *>(a.in) + size_t(r0) * 3 * plane_bytes;
+    // the rhs of the tile that exist: a lane's gathers past them are out of range
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char *>(in), short(0), int(unsigned(min(2 * RT, a.n - r0)) * 3u * plane_bytes), kBufWord3);
+    Real acc_re[RT][3], acc_im[RT][3];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc_re[r][c] = acc_im[r][c] = Real(0);
+    const unsigned hoff = unsigned(h * RT * 3) * plane_bytes;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+      const uint4 nb = reinterpret_cast<const uint4 *>(nbt)[mu * 32 + si];
+      Lnk<Real> Lk;
+      load_link<Real, LT, false, false>(sl, link_plane(mu, recon), 32u, unsigned(si), Lk);
+      apply_hop_buf32<Real, RT, false>(Lk, rs, plane_bytes, nb.x + hoff, acc_re, acc_im);
+      load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 32u, unsigned(si), Lk);
+      apply_hop_buf32<Real, RT, true>(Lk, rs, plane_bytes, nb.y + hoff, acc_re, acc_im);
+      load_naik_lds<Real, LT, R14, 32>(sl, row2, mu, si, Lk);
+      apply_hop_buf32<Real, RT, false>(Lk, rs, plane_bytes, nb.z + hoff, acc_re, acc_im);
+      load_naik_lds<Real, LT, R14, 32>(sl, row2, 4 + mu, si, Lk);
+      apply_hop_buf32<Real, RT, true>(Lk, rs, plane_bytes, nb.w + hoff, acc_re, acc_im);
+    }
+    C *__restrict__ out = static_cast<C *>(a.out) + size_t(r0) * 3 * vh;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      if (!(valid && act[r])) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        C o;
+        o.x = acc_re[r][c];
+        o.y = acc_im[r][c];
+        out[(unsigned)((h * RT + r) * 3 + c) * vh + s] = o;
+      }
+    }
   }
 }
 
@@ -934,6 +1099,20 @@ DslashFn pick_lds_rt(int rt) {
   }
 }
 
+template <typename Real, typename LT, int RT, bool R14, int WPB, bool NT>
+void launch_lds32(const Args &a, dim3 grid, hipStream_t st) {
+  constexpr size_t lds = lds32_nbr_offset<Real, LT, R14>() + kNbrTable32Bytes;
+  k_dslash_lds32<Real, LT, RT, R14, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
+}
+
+// 32-site form: lds 1 = 4 waves, 2 = 8 waves; rhs_per_thread 1 or 2; plain half Dslash only
+template <typename Real, typename LT, bool R14, bool NT>
+DslashFn pick_lds32(int rt, int lds) {
+  if (lds == 1) return rt == 1 ? launch_lds32<Real, LT, 1, R14, 4, NT> : (rt == 2 ? launch_lds32<Real, LT, 2, R14, 4, NT> : nullptr);
+  if (lds == 2) return rt == 1 ? launch_lds32<Real, LT, 1, R14, 8, NT> : (rt == 2 ? launch_lds32<Real, LT, 2, R14, 8, NT> : nullptr);
+  return nullptr;
+}
+
 // lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves, 3 = 16 waves
 template <typename Real, typename LT, bool R14, bool EPI, bool NT>
 DslashFn pick_lds(int rt, int lds) {
@@ -967,10 +1146,12 @@ DslashFn pick_rt(int rt) {
 template <typename Real, typename LT, bool R14>
 DslashFn pick_all(bool epi, int rt, int spb, bool nt, int lds) {
   if (lds) {
+    if (spb == 32) return epi ? nullptr : (nt ? pick_lds32<Real, LT, R14, true>(rt, lds) : pick_lds32<Real, LT, R14, false>(rt, lds));
     if (spb != 64) return nullptr;
     if (nt) return epi ? pick_lds<Real, LT, R14, true, true>(rt, lds) : pick_lds<Real, LT, R14, false, true>(rt, lds);
     return epi ? pick_lds<Real, LT, R14, true, false>(rt, lds) : pick_lds<Real, LT, R14, false, false>(rt, lds);
   }
+  if (spb != 64 && spb != 256) return nullptr;
   if (epi) {
     if (spb == 64) return nt ? pick_rt<Real, LT, R14, true, 64, true>(rt) : pick_rt<Real, LT, R14, true, 64, false>(rt);
     return nt ? pick_rt<Real, LT, R14, true, 256, true>(rt) : pick_rt<Real, LT, R14, true, 256, false>(rt);

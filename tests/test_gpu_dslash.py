@@ -201,6 +201,8 @@ def test_full_size_32c8_sampled_sites():
 
 ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
             + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3, 4, 5, 6) for xm in (0, 1, 2)
+               for nt in (0, 1)]
+            + [(rt, 32, nt, lds, xm) for rt in (1, 2, 4) for lds in (0, 1, 2, 3) for xm in (0, 1, 2)
                for nt in (0, 1)])
 
 
@@ -211,6 +213,8 @@ def _cfg_valid(prec, cfg, dims):
     rt, spb, nt, lds, xm = cfg
     plane = dims[0] // 2 * dims[1]
     if prec == hisq.HISQ_F64 and (rt == 16 or lds >= 4):
+        return False
+    if spb == 32 and not (lds in (1, 2) and rt <= 2):
         return False
     if lds >= 3 and rt > 2:
         return False
@@ -227,7 +231,8 @@ def _cfg_valid(prec, cfg, dims):
 def test_every_launch_config_bit_identical(prec, recon, dims):
     """All register tiles, workgroup shapes, cache hints, the LDS-staged form and the XCD maps give
     the same bits, for the plain half Dslash and for the fused M operator (including its FP64
-    <p, Mp> reduction), and the autotuned choice is one of them.  Exactly the configurations the
+    <p, Mp> reduction; the 32-site form is plain-only and leaves the fused configuration as it
+    was), and the autotuned choice is one of them.  Exactly the configurations the
     header rules out are refused.  (16, 8, 8, 4) admits the z-slab XCD map, (16, 64, 4, 4) the
     y-slab map; (6, 6, 4, 6) has V/2 = 432, so the last 64-site block of the LDS forms is ragged."""
     n, mass = 11, 0.1

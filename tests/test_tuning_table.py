@@ -20,7 +20,8 @@ def test_shipped_tuning_table_format():
         assert (lx, ly, lz, lt) in lattices
         assert prec in (0, 1, 2) and recon in (14, 18) and (prec != 0 or recon == 18)
         assert 1 <= n <= 64 and fused in (0, 1)
-        assert rt in (1, 2, 4, 8, 16) and spb in (64, 256) and nt in (0, 1)
+        assert rt in (1, 2, 4, 8, 16) and spb in (32, 64, 256) and nt in (0, 1)
+        assert spb != 32 or (lds in (1, 2) and rt <= 2 and fused == 0)
         assert 0 <= lds <= 6 and 0 <= xm <= 2 and (xm == 0 or lds > 0)
         assert not (prec == 0 and (rt == 16 or lds >= 4))
         assert ms > 0

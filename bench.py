@@ -79,6 +79,27 @@ def measured_traffic(config_tuple):
         return None
 
 
+def chained_launch_ms(lat, hisq, torch, prec, v_e, w_o, w_e, steps=10):
+    """Mean launch time of `steps` pairs D_oe (w_e -> w_o), D_eo (w_o -> w_e), each launch reading
+    what the one before wrote, timed with HIP events on the launch stream.  The start is v_e
+    scaled by 1e-25: D grows a vector by at most ~9 per application, so the 2 (steps + 2)
+    launches stay within normal FP32 numbers."""
+    w_e.copy_(v_e)
+    w_e.mul_(1e-25)
+    for _ in range(2):
+        lat.dslash(1, prec, w_e, w_o)
+        lat.dslash(0, prec, w_o, w_e)
+    torch.cuda.synchronize()
+    t0, t1 = _events(torch)
+    t0.record()
+    for _ in range(steps):
+        lat.dslash(1, prec, w_e, w_o)
+        lat.dslash(0, prec, w_o, w_e)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / (2 * steps)
+
+
 SWEEP_N = (1, 2, 4, 8, 16)
 
 
@@ -390,6 +411,7 @@ def main():
     ms_step, ms_launch, ms_iso = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
                                                     args.steps, args.warmup)
     clocks = gpu_clocks()  # sampled right after the timed region
+    ms_chain = chained_launch_ms(lat, hisq, torch, hisq.HISQ_F32, v_e, w_o, w_e)
     launch_cfg = hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)
     flops_step = 2 * pm.half_dslash_flops(vh, n)
     gflops = flops_step / (ms_step * 1e-3) / 1e9
@@ -423,6 +445,12 @@ def main():
                      "bytes_per_launch": bytes_launch, "ms_per_launch": round(ms_launch, 5),
                      "ms_per_launch_event_bracketed": round(ms_iso, 5)},
         "gpu_clocks_after_timed_region": clocks,
+        # context, not the value: the same launches with each input written by the launch before
+        # (D_oe then D_eo of its result, as the CG applies M), where the input is still cached
+        "dslash_chained_as_in_cg": {
+            "ms_per_launch": round(ms_chain, 5),
+            "compulsory_GBps": round(bytes_launch / (ms_chain * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(bytes_launch / (ms_chain * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
     }
 
     if not args.no_sweep:

@@ -22,3 +22,19 @@ def test_tiled_links_repeat_the_small_field():
 def test_tiled_links_need_multiples_of_4():
     with pytest.raises(ValueError):
         synth.tiled_gauge_links((6, 4, 4, 4), 1)
+
+
+def test_naik_links_have_the_14_real_form():
+    """Reading of the 14-real Naik format: for N = c U with U in SU(3), row 2 of N equals
+    z conj(row0 x row1) with z = c / conj(c)^2 (z = -24 for the synthetic N = -U/24)."""
+    fat, naik = synth.gauge_links((4, 4, 4, 4), 21)
+    n = naik.reshape(-1, 3, 3)
+    cross = np.conj(np.cross(n[:, 0, :], n[:, 1, :]))
+    assert np.max(np.abs(n[:, 2, :] - (-24.0) * cross)) <= 1e-14
+    u = -24.0 * n  # SU(3): unitary with determinant 1
+    eye = np.eye(3)
+    assert np.max(np.abs(u @ np.conj(np.transpose(u, (0, 2, 1))) - eye)) <= 1e-13
+    assert np.max(np.abs(np.linalg.det(u) - 1.0)) <= 1e-13
+    # fat links are not of that form (the 14-real storage must not apply to them)
+    f = fat.reshape(-1, 3, 3)
+    assert np.max(np.abs(f[:, 2, :] - np.conj(np.cross(f[:, 0, :], f[:, 1, :])))) > 1e-2

@@ -20,7 +20,8 @@
  *   vectors: [n][3][V/2] complex (complex128 for HISQ_F64, complex64 otherwise) on the sites of
  *            one parity: right-hand side major, then colour, then site; the site index within a
  *            parity is lex >> 1.  Right-hand side i of a bundle is therefore a pointer offset of
- *            i*3*(V/2) complex elements.
+ *            i*3*(V/2) complex elements.  Vector pointers must be multiples of their complex
+ *            element size (8 bytes for complex64, 16 for complex128; HISQ_ERR_ARG otherwise).
  *
  * Ownership and streams: every vector pointer is device memory owned by the caller.  The
  * context copies the links on hisq_load_links (the caller may free its buffers afterwards) and

@@ -497,6 +497,9 @@ extern "C" int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, cons
   if (!ctx) return HISQ_ERR_ARG;
   if (!a || !b || !dots) return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: null pointer");
   if (!prec_valid(prec)) return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: bad precision %d", prec);
+  if (!elem_aligned(a, cplx_bytes(prec)) || !elem_aligned(b, cplx_bytes(prec)) || !elem_aligned(dots, sizeof(double)))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: vectors must be aligned to %zu bytes, dots to 8",
+                   cplx_bytes(prec));
   if (n < 1 || n > HISQ_MAX_RHS)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs: n = %d outside 1..%d", n, HISQ_MAX_RHS);
   const int nblk = blas_nblk(ctx);

@@ -249,6 +249,8 @@ extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, vo
   if (!ctx) return HISQ_ERR_ARG;
   if (!b || !x || !prm) return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: null pointer");
   if (b == x) return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: b and x alias");
+  if (!elem_aligned(b, 16) || !elem_aligned(x, 16))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: b and x must be aligned to 16 bytes");
   if (n < 1 || n > HISQ_MAX_RHS)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_cg_mrhs: n = %d outside 1..%d", n, HISQ_MAX_RHS);
   if (!(prm->tol > 0) || prm->max_iter < 1 || !std::isfinite(mass))
@@ -288,6 +290,8 @@ extern "C" int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b,
   if (!ctx) return HISQ_ERR_ARG;
   if (!b || !r_out || !y_out || n < 1 || n > HISQ_MAX_RHS || n_snap < 1 || snap_every < 1 || !(tol > 0))
     return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_harvest: bad argument");
+  if (!elem_aligned(b, 16) || !elem_aligned(r_out, 16) || !elem_aligned(y_out, 16))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_harvest: b, r_out and y_out must be aligned to 16 bytes");
   if (!ctx->links_loaded || !ctx->links[HISQ_F64].base)
     return set_err(ctx, HISQ_ERR_STATE, "hisq_nn_harvest: the FP64 link copy is required");
   HIPCHK(ctx, hipSetDevice(ctx->device));

@@ -399,6 +399,8 @@ extern "C" int hisq_dslash_mrhs(hisq_ctx *ctx, int out_parity, int prec, int n, 
   if (out_parity != 0 && out_parity != 1)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_dslash_mrhs: out_parity must be 0 or 1");
   if (!prec_valid(prec)) return set_err(ctx, HISQ_ERR_ARG, "hisq_dslash_mrhs: bad precision %d", prec);
+  if (!elem_aligned(in, cplx_bytes(prec)) || !elem_aligned(out, cplx_bytes(prec)))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_dslash_mrhs: vectors must be aligned to %zu bytes", cplx_bytes(prec));
   if (n < 1 || n > HISQ_MAX_RHS)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_dslash_mrhs: n = %d outside 1..%d", n, HISQ_MAX_RHS);
   if (!ctx->links_loaded) return set_err(ctx, HISQ_ERR_STATE, "hisq_dslash_mrhs: no links loaded");
@@ -411,6 +413,10 @@ extern "C" int hisq_apply_m(hisq_ctx *ctx, int prec, double mass, int n, const v
   if (!in || !out) return set_err(ctx, HISQ_ERR_ARG, "hisq_apply_m: null vector pointer");
   if (in == out) return set_err(ctx, HISQ_ERR_ARG, "hisq_apply_m: in and out alias");
   if (!prec_valid(prec)) return set_err(ctx, HISQ_ERR_ARG, "hisq_apply_m: bad precision %d", prec);
+  if (!elem_aligned(in, cplx_bytes(prec)) || !elem_aligned(out, cplx_bytes(prec)) ||
+      !elem_aligned(pq_out, sizeof(double)))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_apply_m: vectors must be aligned to %zu bytes, pq_out to 8",
+                   cplx_bytes(prec));
   if (n < 1 || n > HISQ_MAX_RHS)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_apply_m: n = %d outside 1..%d", n, HISQ_MAX_RHS);
   if (!ctx->links_loaded) return set_err(ctx, HISQ_ERR_STATE, "hisq_apply_m: no links loaded");

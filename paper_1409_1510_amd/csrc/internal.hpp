@@ -136,3 +136,6 @@ int launch_dot_partials(hisq_ctx *ctx, int prec, int n, const void *a, const voi
 
 bool prec_valid(int prec);
 size_t cplx_bytes(int prec);
+// vector arguments are arrays of complex elements: their addresses must be multiples of the
+// element size (8 bytes complex64, 16 bytes complex128); nullptr counts as aligned
+inline bool elem_aligned(const void *p, size_t elem) { return reinterpret_cast<size_t>(p) % elem == 0; }

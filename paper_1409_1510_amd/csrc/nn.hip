@@ -1477,6 +1477,8 @@ extern "C" int hisq_nn_apply(hisq_ctx *ctx, int n, int prec_io, const void *r, v
   RETCHK(check_nn(ctx, "hisq_nn_apply"));
   if (!r || !z || n < 1 || n > HISQ_MAX_RHS || (prec_io != HISQ_F64 && prec_io != HISQ_F32))
     return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_apply: bad argument");
+  if (!elem_aligned(r, cplx_bytes(prec_io)) || !elem_aligned(z, cplx_bytes(prec_io)))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_apply: r and z must be aligned to %zu bytes", cplx_bytes(prec_io));
   if (prec_io == HISQ_F32) return nn_apply_internal(ctx, n, static_cast<const float2 *>(r), static_cast<float2 *>(z));
   Scratch sc;
   RETCHK(scratch(ctx, n, &sc));
@@ -1494,6 +1496,8 @@ extern "C" int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void
   RETCHK(check_nn(ctx, "hisq_nn_loss_grad"));
   if (!r || !y || n < 1 || n > HISQ_MAX_RHS)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_loss_grad: bad argument");
+  if (!elem_aligned(r, 16) || !elem_aligned(y, 16))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_loss_grad: r and y must be aligned to 16 bytes");
   Scratch sc;
   RETCHK(scratch(ctx, n, &sc));
   RETCHK(nn_batch_grad(ctx, n, r, y, true, sc.loss));
@@ -1509,6 +1513,8 @@ extern "C" int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const vo
   RETCHK(check_nn(ctx, "hisq_nn_train"));
   if (!r || !y || n_pairs < 1 || epochs < 1 || batch < 1 || batch > HISQ_MAX_RHS || !(lr > 0))
     return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_train: bad argument");
+  if (!elem_aligned(r, 16) || !elem_aligned(y, 16))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_nn_train: r and y must be aligned to 16 bytes");
   NNState *s = ctx->nn;
   const size_t vlen = size_t(3) * ctx->g.vh;
   const int nbatches = n_pairs / batch;

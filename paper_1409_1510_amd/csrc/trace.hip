@@ -48,6 +48,7 @@ extern "C" int hisq_z2_noise(hisq_ctx *ctx, unsigned long long seed, long long k
   if (!ctx) return HISQ_ERR_ARG;
   if (!out || n < 1 || n > HISQ_MAX_RHS || k0 < 0)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_z2_noise: need out, 1 <= n <= %d, k0 >= 0", HISQ_MAX_RHS);
+  if (!elem_aligned(out, 16)) return set_err(ctx, HISQ_ERR_ARG, "hisq_z2_noise: out must be aligned to 16 bytes");
   HIPCHK(ctx, hipSetDevice(ctx->device));
   return launch_noise(ctx, seed, k0, n, out);
 }

@@ -104,6 +104,37 @@ def test_max_rhs_and_errors():
     lat.close()
 
 
+def test_misaligned_vectors_rejected():
+    """A vector pointer that is not a multiple of its complex element size is refused with
+    HISQ_ERR_ARG before anything is launched (the offset buffers stay in bounds either way)."""
+    import ctypes
+    dims = (4, 4, 4, 4)
+    lat, fat, naik = make_lattice(dims, 111)
+    lib = hisq.library()
+    vp = ctypes.c_void_p
+    for prec, dt, off in ((hisq.HISQ_F64, torch.complex128, 8), (hisq.HISQ_F32, torch.complex64, 4)):
+        a = torch.zeros((2, 3, lat.vh), dtype=dt, device=DEV)
+        b = torch.zeros_like(a)
+        mis = vp(a.data_ptr() + off)
+        assert lib.hisq_dslash_mrhs(lat.ctx, 1, prec, 1, mis, hisq._ptr(b)) == hisq.HISQ_ERR_ARG
+        assert lib.hisq_dslash_mrhs(lat.ctx, 1, prec, 1, hisq._ptr(b), mis) == hisq.HISQ_ERR_ARG
+        assert "aligned" in lib.hisq_last_error(lat.ctx).decode()
+        assert lib.hisq_apply_m(lat.ctx, prec, 0.1, 1, mis, hisq._ptr(b), None) == hisq.HISQ_ERR_ARG
+        dots = torch.zeros(4, dtype=torch.float64, device=DEV)
+        assert lib.hisq_dot_mrhs(lat.ctx, prec, 1, mis, hisq._ptr(b), hisq._ptr(dots)) == hisq.HISQ_ERR_ARG
+        assert lib.hisq_dot_mrhs(lat.ctx, prec, 1, hisq._ptr(a), hisq._ptr(b), vp(dots.data_ptr() + 4)) == hisq.HISQ_ERR_ARG
+    x = torch.zeros((2, 3, lat.vh), dtype=torch.complex128, device=DEV)
+    y = torch.zeros_like(x)
+    prm = hisq.hisq_cg_params(kind=hisq.HISQ_CG_F64, tol=1e-8, max_iter=10, reliable_every=50,
+                              link_prec=hisq.HISQ_F32, use_x0=0, check_every=0)
+    assert lib.hisq_cg_mrhs(lat.ctx, 0.1, 1, vp(x.data_ptr() + 8), hisq._ptr(y), ctypes.byref(prm), None) == hisq.HISQ_ERR_ARG
+    assert lib.hisq_z2_noise(lat.ctx, 1, 0, 1, vp(x.data_ptr() + 8)) == hisq.HISQ_ERR_ARG
+    # the aligned calls still work afterwards
+    assert lib.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, 1, hisq._ptr(x), hisq._ptr(y)) == hisq.HISQ_OK
+    torch.cuda.synchronize()
+    lat.close()
+
+
 def test_state_and_link_errors():
     dims = (4, 4, 4, 4)
     lat = hisq.Lattice(dims, 0)

@@ -370,10 +370,15 @@ def main():
                     help="training epochs of the solver study (0: 20)")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
-                         "kernel (counter calibration), then --steps FP32 Dslash steps")
+                         "kernel (counter calibration), 100 ms of untimed steps with another "
+                         "rhs_per_thread, then --steps FP32 Dslash steps")
     ap.add_argument("--profile-sweep", action="store_true",
-                    help="short run for rocprofv3: the counter-calibration kernel, then 3 steps of "
-                         "every case of the n/precision sweep (after 1 warm-up step each)")
+                    help="short run for rocprofv3: the counter-calibration kernel, then for every "
+                         "case of the n/precision sweep 50 ms of untimed steps, 1 warm-up step and "
+                         "3 steps")
+    ap.add_argument("--profile-nn", action="store_true",
+                    help="only the learned preconditioner's Gram application at 48^3x12 on 16 rhs, "
+                         "2 + --steps times (for a rocprofv3 run)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="short run for rocprofv3: the 32^3x8 mixed CG (FP16 links, 8 rhs) of the "
                          "benchmark, solved twice")
@@ -405,6 +410,26 @@ def main():
             print(f"profile-cg solve: {time.perf_counter() - t:.3f} s, {max(info['iters'])} iterations",
                   flush=True)
         lat2.close()
+        return
+    if args.profile_nn:
+        # the learned preconditioner's Gram application (two network passes, BF16 activations,
+        # FP16 links) on 16 rhs at 48^3 x 12, as inside the flexible CG; the kernels' time does
+        # not depend on the weights, so the network keeps its initial ones
+        dims3 = synth.WORKLOADS["c3"]["dims"]
+        fat3, naik3 = synth.tiled_gauge_links(dims3, 7)
+        lat3 = hisq.Lattice(dims3, 0)
+        lat3.load_links(fat3, naik3, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 18)
+        del fat3, naik3
+        lib = hisq.library()
+        hisq._check(lat3.ctx, lib.hisq_nn_init(lat3.ctx, 4, 8, 5))
+        hisq._check(lat3.ctx, lib.hisq_nn_set_form(lat3.ctx, hisq.HISQ_NN_FORM_GRAM))
+        r = torch.randn(16, 3, lat3.vh, dtype=torch.complex64, device="cuda:0")
+        z = torch.empty_like(r)
+        for k in range(2 + args.steps):
+            hisq._check(lat3.ctx, lib.hisq_nn_apply(lat3.ctx, 16, hisq.HISQ_F32, hisq._ptr(r), hisq._ptr(z)))
+        torch.cuda.synchronize()
+        print(f"profile-nn done: {2 + args.steps} Gram applications on 16 rhs, lattice {dims3}", flush=True)
+        lat3.close()
         return
     if args.workload in ("c3", "c4"):
         print(json.dumps(solver_study(args, torch, synth, hisq, pm)))

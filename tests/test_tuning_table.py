@@ -30,3 +30,30 @@ def test_shipped_tuning_table_format():
         seen.add(key)
         count += 1
     assert count >= 50
+
+
+def test_committed_kernel_profile_matches_sources_and_table():
+    """The committed rocprofv3 summary of the benchmarked kernel was taken on the current kernel
+    sources (bench.py reports its HBM traffic only then) and in the launch configuration the
+    shipped table gives the benchmark's case (32^3 x 8, FP32, 18-real Naik, 16 rhs, plain form);
+    its counter traffic is at least the compulsory bytes of that launch."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    fields = {}
+    for line in open(bench.PROFILE_SUMMARY):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    assert fields["kernel_source_sha256_16"] == bench.kernel_source_hash()
+    cfg = None
+    for line in open(os.path.join(root, "paper_1409_1510_amd", "tuning", "gfx950.txt")):
+        f = line.split()
+        if f and not f[0].startswith("#") and list(map(int, f[:8])) == [32, 32, 32, 8, 1, 18, 16, 0]:
+            cfg = tuple(map(int, f[8:13]))
+    assert cfg is not None and fields["launch_config"] == str(cfg)
+    traffic = bench.measured_traffic(cfg)
+    compulsory = 32 * 32 * 32 * 8 // 2 * (1152 + 48 * 16)
+    assert traffic is not None and traffic >= compulsory
+    assert int(fields["algorithmic_bytes_per_launch"]) == compulsory

@@ -387,13 +387,19 @@ def test_tuning_table_round_trip(tmp_path):
     lat2.close()
 
 
-def _launch_ms(lat, prec, n, reps=20):
-    a = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device=DEV)
+def _launch_ms(lat, prec, n, reps=20, sustain_ms=50.0):
+    """Mean launch time of D_oe, D_eo pairs after `sustain_ms` of the same launches untimed (the
+    device reaches its sustained speed for these kernels after some 30 ms of load)."""
+    import time
+    a = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device=DEV) * 1e-30
     b = torch.empty_like(a)
-    for _ in range(3):
-        lat.dslash(1, prec, a, b)
-        lat.dslash(0, prec, b, a)
-    torch.cuda.synchronize()
+    t = time.perf_counter()
+    while (time.perf_counter() - t) * 1e3 < sustain_ms:
+        for _ in range(5):
+            lat.dslash(1, prec, a, b)
+            lat.dslash(0, prec, b, a)
+        torch.cuda.synchronize()
+        a.mul_(1e-30)  # D grows a vector by at most ~9 per application: stay far from overflow
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):

@@ -20,6 +20,8 @@ device needs ~30 ms of load to reach its sustained speed for this kernel.
   cpu_baseline  : the FP64 numpy oracle's half Dslash on a bounded sample of the same lattice.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-sweep]
+       python bench.py --workload c3|c4          (solver study at 48^3x12 / 64^3x16)
+       python bench.py --profile|--profile-sweep|--profile-nn|--profile-cg   (short runs for rocprofv3)
 """
 from __future__ import annotations
 

@@ -303,13 +303,17 @@ class Lattice:
     def empty(self, n, prec=HISQ_F64):
         return self.torch.empty((n, 3, self.vh), dtype=self.vec_dtype(prec), device=self.device)
 
-    def _vec(self, v, prec, name="vector"):
+    def _vec(self, v, prec, name="vector", n=None):
+        """Check a vector argument: device, dtype of the precision, contiguous [n][3][V/2] (with
+        the given n if any: the library reads or writes exactly that many rhs)."""
         if not v.is_cuda or v.device != self.device:
             raise ValueError(f"{name} must live on {self.device}")
         if str(v.dtype) != _VEC_DTYPE[prec]:
             raise ValueError(f"{name} must be {_VEC_DTYPE[prec]} for precision {prec}, got {v.dtype}")
         if v.dim() != 3 or v.shape[1] != 3 or v.shape[2] != self.vh or not v.is_contiguous():
             raise ValueError(f"{name} must be contiguous [n][3][{self.vh}], got {tuple(v.shape)}")
+        if n is not None and v.shape[0] != n:
+            raise ValueError(f"{name} must hold {n} right-hand sides, got {v.shape[0]}")
         return v
 
     def load_links(self, fat, naik, copies=HISQ_LINKS_ALL, naik_recon=18):
@@ -325,7 +329,7 @@ class Lattice:
     def dslash(self, out_parity, prec, v_in, out=None):
         self._vec(v_in, prec, "in")
         n = v_in.shape[0]
-        out = self.empty(n, prec) if out is None else self._vec(out, prec, "out")
+        out = self.empty(n, prec) if out is None else self._vec(out, prec, "out", n)
         hisq_set_stream(self.ctx)
         hisq_dslash_mrhs(self.ctx, out_parity, prec, n, v_in, out)
         return out
@@ -333,7 +337,7 @@ class Lattice:
     def apply_m(self, prec, mass, v_in, out=None, with_pq=False):
         self._vec(v_in, prec, "in")
         n = v_in.shape[0]
-        out = self.empty(n, prec) if out is None else self._vec(out, prec, "out")
+        out = self.empty(n, prec) if out is None else self._vec(out, prec, "out", n)
         pq = self.torch.empty(n, dtype=self.torch.float64, device=self.device) if with_pq else None
         hisq_set_stream(self.ctx)
         hisq_apply_m(self.ctx, prec, mass, n, v_in, out, pq)
@@ -341,8 +345,8 @@ class Lattice:
 
     def dot(self, prec, a, b):
         self._vec(a, prec, "a")
-        self._vec(b, prec, "b")
         n = a.shape[0]
+        self._vec(b, prec, "b", n)
         d = self.torch.empty(2 * n, dtype=self.torch.float64, device=self.device)
         hisq_set_stream(self.ctx)
         hisq_dot_mrhs(self.ctx, prec, n, a, b, d)
@@ -369,7 +373,7 @@ class Lattice:
            link_prec=HISQ_F32, x0=None, check_every=0):
         self._vec(b, HISQ_F64, "b")
         n = b.shape[0]
-        x = self.empty(n, HISQ_F64) if x0 is None else self._vec(x0.clone(), HISQ_F64, "x0")
+        x = self.empty(n, HISQ_F64) if x0 is None else self._vec(x0.clone(), HISQ_F64, "x0", n)
         p = hisq_cg_params(kind, tol, max_iter, reliable_every, link_prec, 0 if x0 is None else 1,
                            check_every)
         iters = (ctypes.c_int * n)()

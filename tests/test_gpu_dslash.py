@@ -135,6 +135,27 @@ def test_misaligned_vectors_rejected():
     lat.close()
 
 
+def test_binding_rejects_mismatched_rhs_counts():
+    """The binding checks that every vector of a call holds the rhs count the library will read
+    or write (a shorter output would be written past its end), before anything is launched."""
+    dims = (4, 4, 4, 4)
+    lat, fat, naik = make_lattice(dims, 112)
+    a = torch.zeros((2, 3, lat.vh), dtype=torch.complex128, device=DEV)
+    short = torch.zeros((1, 3, lat.vh), dtype=torch.complex128, device=DEV)
+    with pytest.raises(ValueError):
+        lat.dslash(1, hisq.HISQ_F64, a, short)
+    with pytest.raises(ValueError):
+        lat.apply_m(hisq.HISQ_F64, 0.1, a, short)
+    with pytest.raises(ValueError):
+        lat.dot(hisq.HISQ_F64, a, short)
+    with pytest.raises(ValueError):
+        lat.cg(0.1, a, x0=short)
+    with pytest.raises(ValueError):  # wrong dtype for the precision
+        lat.dslash(1, hisq.HISQ_F32, a)
+    torch.cuda.synchronize()
+    lat.close()
+
+
 def test_state_and_link_errors():
     dims = (4, 4, 4, 4)
     lat = hisq.Lattice(dims, 0)

@@ -322,6 +322,11 @@ class Lattice:
             naik = np.ascontiguousarray(naik, np.complex128)
             if fat.shape != (self.volume, 4, 3, 3) or naik.shape != fat.shape:
                 raise ValueError(f"links must be [{self.volume}][4][3][3]")
+        else:  # device tensors: the library reads V * 36 complex128 from each
+            for name, t in (("fat", fat), ("naik", naik)):
+                if (str(t.dtype) != "torch.complex128" or tuple(t.shape) != (self.volume, 4, 3, 3)
+                        or not t.is_contiguous()):
+                    raise ValueError(f"{name} links must be contiguous complex128 [{self.volume}][4][3][3]")
         hisq_load_links(self.ctx, fat, naik, copies, naik_recon)
         if os.path.exists(TUNING_PATH) and os.environ.get("HISQ_AUTOTUNE", "1") != "0":
             hisq_load_tuning(self.ctx, TUNING_PATH)

@@ -185,6 +185,8 @@ def test_links_from_device_memory():
     fat, naik = synth.gauge_links(dims, 111)
     lat = hisq.Lattice(dims, 0)
     lat.load_links(torch.from_numpy(fat).to(DEV), torch.from_numpy(naik).to(DEV))
+    with pytest.raises(ValueError):  # a device array of the wrong size is refused by the binding
+        lat.load_links(torch.from_numpy(fat[:-1]).to(DEV), torch.from_numpy(naik[:-1]).to(DEV))
     v = _vecs(dims, 2, 112)
     got = lat.dslash(0, hisq.HISQ_F64, torch.from_numpy(v).to(DEV)).cpu().numpy()
     assert rel_elem(got, oracle.dslash_half(fat, naik, v, dims, 0)) <= 1e-13

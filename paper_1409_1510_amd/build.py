@@ -29,9 +29,17 @@ FLAGS = [
 ]
 
 
+# per-unit scheduler: the FP64 Dslash instances are scheduled for instruction-level parallelism
+# (LLVM's max-ilp strategy), which issues their 16-byte gathers earlier: measured 11-19 % faster
+# FP64 LDS launches at 8 and 16 rhs (32^3 x 8) and within 1 % at 1-4 rhs.  The FP32 and FP16-link
+# units keep the default strategy, under which their 16-rhs launches are 8-10 % faster than with
+# max-ilp.  Scheduling only orders instructions: every output stays bit-identical.
+EXTRA_FLAGS = {"dslash_f64.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

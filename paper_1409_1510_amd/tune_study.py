@@ -2,6 +2,7 @@
 paper_1409_1510_amd/tuning/<arch>.txt (loaded by hisq.Lattice.load_links).
 
 Usage (on the GPU): python -m paper_1409_1510_amd.tune_study [--out PATH] [--lattices c1,c3,c4]
+                                                         [--precs 0,1,2]
 The timing does not depend on the link values, so the links are a small random field tiled over
 the lattice.
 """
@@ -26,7 +27,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=hisq.TUNING_PATH)
     ap.add_argument("--lattices", default="c1,c3,c4")
+    ap.add_argument("--precs", default="0,1,2",
+                    help="precisions to re-tune (the others keep the entries of the shipped table)")
     args = ap.parse_args()
+    retune = {int(p) for p in args.precs.split(",")}
     os.environ["HISQ_AUTOTUNE"] = "1"
     for name in args.lattices.split(","):
         dims = synth.WORKLOADS[name]["dims"]
@@ -37,6 +41,8 @@ def main():
                            hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, recon)
             precs = (0, 1, 2) if recon == 18 else (1, 2)
             for prec in precs:
+                if prec not in retune:
+                    continue
                 for n in RHS[name]:
                     hisq.hisq_set_launch(lat.ctx, prec, n, None)  # clears both forms
                     for fused in (0, 1):

@@ -93,6 +93,27 @@ def test_per_rhs_stop_zero_rhs_and_warm_start():
     lat.close()
 
 
+@pytest.mark.parametrize("kind", [hisq.HISQ_CG_F64, hisq.HISQ_CG_MIXED])
+def test_max_rhs_bundle(kind):
+    """A full bundle of HISQ_MAX_RHS rhs (4^4 x 6 lattice): every rhs reaches the tolerance in the
+    oracle's true residual, and rhs i of the bundle gets the same iterations as the same source
+    solved alone (the per-rhs scalars do not mix)."""
+    dims, mass, tol = (4, 4, 4, 6), 0.1, 1e-8
+    lat, fat, naik = make_lattice(dims, 210)
+    n = hisq.HISQ_MAX_RHS
+    b = synth.sources(dims, n, 211)
+    x, info = _solve(lat, mass, b, kind=kind, tol=tol, link_prec=hisq.HISQ_F32)
+    assert info["rc"] == 0 and all(info["converged"])
+    res = oracle.true_residual(fat, naik, x, b, dims, mass)
+    assert np.all(res <= tol)
+    if kind == hisq.HISQ_CG_F64:
+        for i in (0, n - 1):
+            xi, infoi = _solve(lat, mass, b[i:i + 1], kind=kind, tol=tol)
+            assert infoi["iters"][0] == info["iters"][i]
+            assert np.array_equal(xi[0], x[i])
+    lat.close()
+
+
 def test_nonfinite_source_rejected():
     dims = (4, 4, 4, 4)
     lat, fat, naik = make_lattice(dims, 206)

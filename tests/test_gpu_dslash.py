@@ -95,6 +95,14 @@ def test_max_rhs_and_errors():
                               torch.from_numpy(v).to(DEV))
     assert e.value.code == hisq.HISQ_ERR_ARG
     x = torch.from_numpy(v[:1]).to(DEV)
+    for bad_n in (0, -1):  # an empty bundle is an argument error, not a no-op launch
+        for fn in (lambda: hisq.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, bad_n, x, x.clone()),
+                   lambda: hisq.hisq_apply_m(lat.ctx, hisq.HISQ_F64, 0.1, bad_n, x, x.clone(), None),
+                   lambda: hisq.hisq_dot_mrhs(lat.ctx, hisq.HISQ_F64, bad_n, x, x,
+                                              torch.zeros(2, dtype=torch.float64, device=DEV))):
+            with pytest.raises(hisq.HisqError) as e:
+                fn()
+            assert e.value.code == hisq.HISQ_ERR_ARG
     with pytest.raises(hisq.HisqError) as e:
         hisq.hisq_dslash_mrhs(lat.ctx, 1, hisq.HISQ_F64, 1, x, x)
     assert e.value.code == hisq.HISQ_ERR_ARG

@@ -145,3 +145,33 @@ def workload_inputs(name: str, n: int | None = None):
     nr = cfg["n"] if n is None else n
     b = sources(cfg["dims"], nr, seed + 1, cfg["source"])
     return cfg, fat, naik, b
+
+
+def gauge_rotated(fat, naik, dims, seed: int, pool: int = 4096):
+    """Random local SU(3) rotation of a link field (the same field in another gauge):
+    X(x, mu) -> W(x) X(x, mu) W(x + mu)^dag and N(x, mu) -> W(x) N(x, mu) W(x + 3 mu)^dag, with
+    W(x) drawn per site from `pool` Haar SU(3) matrices.  Applied to a tiled field it gives links
+    that no longer repeat with the tile's period, so a link read from a site shifted by a multiple
+    of the period shows up.  Returns new arrays; the inputs are not changed."""
+    check_dims(dims)
+    lx, ly, lz, lt = dims
+    v = volume(dims)
+    gen = _gen(seed)
+    w = haar_su3(gen, pool)
+    which = gen.integers(0, pool, size=v)
+    wd = _dagger(w)
+    ext = (lx, ly, lz, lt)
+    stride = (1, lx, lx * ly, lx * ly * lz)
+    out_f = np.empty_like(fat)
+    out_n = np.empty_like(naik)
+    chunk = 1 << 18
+    for lo in range(0, v, chunk):
+        lex = np.arange(lo, min(v, lo + chunk), dtype=np.int64)
+        coord = (lex % lx, (lex // lx) % ly, (lex // (lx * ly)) % lz, lex // (lx * ly * lz))
+        left = w[which[lex]]
+        for mu in range(4):
+            for src, dst, hop in ((fat, out_f, 1), (naik, out_n, 3)):
+                c = coord[mu]
+                nb = lex + (((c + hop) % ext[mu]) - c) * stride[mu]
+                dst[lex, mu] = left @ src[lex, mu] @ wd[which[nb]]
+    return out_f, out_n

@@ -187,3 +187,25 @@ def test_c3_mixed_full_size_true_residual(link_prec):
     print(f"c3 mixed link_prec {link_prec}: iters {info['iters']}, oracle residual {res}")
     assert np.all(res <= tol)
     lat.close()
+
+
+@pytest.mark.timeout(900)
+def test_c4_mixed_full_size_true_residual():
+    """64^3 x 16, m = 0.005, links with eps = 0.3, 2 complex Gaussian rhs of the 32 (the CPU
+    check of the solution takes ~20 s per rhs): the mixed solver with FP16 link storage (moving to
+    the FP32 links if the FP16 error dominates) reaches a true FP64 residual <= 1e-8 as measured
+    by the oracle's M on the GPU's solution."""
+    cfg = synth.WORKLOADS["c4"]
+    dims, mass, tol = cfg["dims"], cfg["mass"], cfg["tol"]
+    seed = synth.workload_seed("c4")
+    lat, fat, naik = make_lattice(dims, seed, eps=cfg["eps"])
+    b = synth.sources(dims, 2, seed + 1, cfg["source"])
+    x, info = _solve(lat, mass, b, kind=hisq.HISQ_CG_MIXED, tol=tol, link_prec=hisq.HISQ_F16,
+                     max_iter=60000)
+    print(f"c4 mixed: {info['seconds']:.1f} s, iters {info['iters']}, FP32 links from iteration "
+          f"{info['link_switch_iter']}, library residuals {info['true_resid']}", flush=True)
+    assert info["rc"] == 0, info
+    lat.close()
+    res = oracle.true_residual(fat, naik, x, b, dims, mass)
+    print(f"c4 mixed: oracle residual {res}")
+    assert np.all(res <= tol)

@@ -38,3 +38,30 @@ def test_naik_links_have_the_14_real_form():
     # fat links are not of that form (the 14-real storage must not apply to them)
     f = fat.reshape(-1, 3, 3)
     assert np.max(np.abs(f[:, 2, :] - np.conj(np.cross(f[:, 0, :], f[:, 1, :])))) > 1e-2
+
+
+def test_gauge_rotated_tiled_links_lose_the_period():
+    """The rotated tiled field no longer repeats with period 4, the Naik links keep the 14-real
+    form (-1/24 times an SU(3) matrix), and it is the same field in another gauge: the oracle's
+    D on the rotated links applied to W v equals W (D v), with W the per-site rotation drawn
+    from the same seed."""
+    import oracle
+    dims = (8, 4, 4, 8)
+    fat, naik = synth.tiled_gauge_links(dims, 11)
+    rf, rn = synth.gauge_rotated(fat, naik, dims, 12)
+    lx, ly, lz, lt = dims
+    shift = 4 * lx * ly * lz  # one tile along t
+    assert np.max(np.abs(rf[:shift] - rf[shift:2 * shift])) > 0.1
+    assert np.max(np.abs(rn[:shift] - rn[shift:2 * shift])) > 0.1 / 24
+    n = rn.reshape(-1, 3, 3)
+    assert np.max(np.abs(n[:, 2, :] - (-24.0) * np.conj(np.cross(n[:, 0, :], n[:, 1, :])))) <= 1e-13
+    # the rotation the generator draws for this seed (same stream, same order)
+    vol = int(np.prod(dims))
+    gen = synth._gen(12)
+    w = synth.haar_su3(gen, 4096)
+    which = gen.integers(0, 4096, size=vol)
+    om = w[which]
+    v = synth.complex_normal(np.random.default_rng(3), (vol, 3))
+    dv = oracle.dslash_full(fat, naik, v, dims)
+    d_rot = oracle.dslash_full(rf, rn, np.einsum("sab,sb->sa", om, v), dims)
+    assert np.max(np.abs(d_rot - np.einsum("sab,sb->sa", om, dv))) <= 1e-12 * np.max(np.abs(dv))

@@ -5,23 +5,29 @@ Workload (default): the 32^3 x 8 lattice with 16 complex Gaussian right-hand sid
 Haar SU(3) Naik links).  One step = one full-lattice multi-rhs Dslash w = D v for the bundle:
 the two half Dslash launches D_oe (even -> odd) and D_eo (odd -> even).
 value = Gflop/s under the 1146 flop per site per rhs convention (Section 1, Table 1 model).
-
-Also reported on the same JSON line:
-  roofline      : compulsory HBM bytes per half-Dslash launch / mean launch duration (HIP events
-                  at the ends of the timed region on the launch stream, over its launches),
-                  against 8 TB/s; the GPU clocks rocm-smi reports under the same load;
 The timed steps follow RAMP_MS of untimed back-to-back steps and then the warmup steps: the
 device needs ~30 ms of load to reach its sustained speed for this kernel.
-  dslash_sweep  : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
-  cg            : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
-                  the mixed-precision solver (FP16 and FP32 links) and the plain FP64 solver;
-  trace_minv    : Tr M^-1 on the same lattice from 64 Z2 noise vectors (Eq. 2), with its error;
-  volume_sweep  : the FP32 half Dslash against the lattice volume;
-  cpu_baseline  : the FP64 numpy oracle's half Dslash on a bounded sample of the same lattice.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-sweep]
-       python bench.py --workload c3|c4          (solver study at 48^3x12 / 64^3x16)
-       python bench.py --profile|--profile-sweep|--profile-nn|--profile-cg   (short runs for rocprofv3)
+Also reported on the same JSON line:
+  roofline       : compulsory HBM bytes per half-Dslash launch / mean launch duration (HIP events
+                   at the ends of the timed region on the launch stream, over its launches),
+                   against 8 TB/s; the GPU clocks rocm-smi reports under the same load;
+  dslash_sweep   : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
+  volume_sweep   : the FP32 half Dslash against the lattice volume;
+  cg             : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
+                   the mixed-precision solver (FP16 and FP32 links) and the plain FP64 solver;
+  trace_minv     : Tr M^-1 on the same lattice from 64 Z2 noise vectors (Eq. 2), with its error;
+  cg_48x48x48x12 : seconds per rhs to 1e-8 at 48^3 x 12, m = 0.01, 16 Z2 rhs: plain FP64, mixed
+                   (FP16 and FP32 links) and the flexible CG with the learned preconditioner,
+                   trained here on pairs harvested from plain CG, with iterations and peak memory;
+  cpu_baseline   : the FP64 numpy oracle on the host's cores (a process per core): the same
+                   whole-lattice Dslash per rhs, and the oracle CG (8^4 in full, 32^3 x 8 per rhs
+                   extrapolated from a timed sample).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-c3] [--no-cpu] [--no-sweep]
+       python bench.py --workload c3|c4 [--nn-variants gram:4,gram:2,...]   (solver study alone)
+       python bench.py --profile [--profile-dims ..] [--profile-prec ..] | --profile-sweep |
+                       --profile-nn | --profile-cg            (short runs for rocprofv3)
 """
 from __future__ import annotations
 
@@ -205,18 +211,23 @@ STUDY = {
 }
 
 
-def solver_study(args, torch, synth, hisq, pm):
+def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, variants=None,
+                 plain=None, progress_tag=None):
     """48^3x12 (16 Z2 rhs, m = 0.01) or 64^3x16 (32 Gaussian rhs, m = 0.005): CG seconds per rhs
-    to a true FP64 residual 1e-8 for mixed precision (FP16 links), plain FP64 (48^3x12) and the
-    flexible CG with the learned preconditioner (trained here on pairs harvested from plain CG on
-    the same links), with iterations, peak device memory, the Dslash Gflop/s inside each solve
-    and the cost of one network application."""
+    to a true FP64 residual 1e-8 for mixed precision (FP16 and FP32 links), plain FP64 (48^3x12)
+    and the flexible CG with the learned preconditioner (trained here on pairs harvested from plain
+    CG on the same links), with iterations, peak device memory, the Dslash Gflop/s inside each
+    solve and the cost of one network application.  `variants`: (form, layers) of the networks to
+    train and solve with (default: the Gram form with 4 layers); `fcg_link_precs`: the link copies
+    the flexible CG's inner operator is run with (the faster is its result)."""
     import ctypes
-    name = args.workload
     st = STUDY[name]
     cfg = synth.WORKLOADS[name]
     dims, n, mass, tol = cfg["dims"], cfg["n"], cfg["mass"], cfg["tol"]
     seed = synth.workload_seed(name)
+    fcg_link_precs = fcg_link_precs or (hisq.HISQ_F16, hisq.HISQ_F32)
+    variants = variants or [("gram", 4)]
+    plain = st["plain"] if plain is None else plain
     t0 = time.perf_counter()
     fat, naik = synth.gauge_links(dims, seed, eps=cfg["eps"])
     t_gen = time.perf_counter() - t0
@@ -228,10 +239,11 @@ def solver_study(args, torch, synth, hisq, pm):
     out = {"workload": f"{'x'.join(map(str, dims))}, m={mass}, {n} {cfg['source']} rhs, tol {tol}",
            "link_generation_s": round(t_gen, 1)}
     lib = hisq.library()
-    epochs = args.epochs if args.epochs else st["epochs"]
+    epochs = epochs or st["epochs"]
+    tag = progress_tag or name
 
     def progress(msg):
-        print(f"[{name}] {msg}", file=sys.stderr, flush=True)
+        print(f"[{tag}] {msg}", file=sys.stderr, flush=True)
 
     def solve(label, rhs, **kw):
         progress(f"solve {label}")
@@ -241,20 +253,26 @@ def solver_study(args, torch, synth, hisq, pm):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t
         nr = rhs.shape[0]
-        out[label] = {"n_rhs": nr, "s_per_rhs": round(sec / nr, 5), "seconds": round(sec, 3),
-                      "iters_mean": round(float(np.mean(info["iters"])), 1),
-                      "iters_max": max(info["iters"]), "true_resid_max": max(info["true_resid"]),
-                      "converged": sum(info["converged"]), "fell_back": sum(info["fell_back"]),
-                      "reliable_updates": info["reliable_updates"], "rc": info["rc"],
-                      "peak_device_GB": round(info["peak_bytes"] / 1e9, 2),
-                      "fp32_links_from_iter": info["link_switch_iter"],
-                      "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
-        return x, info
+        res = {"n_rhs": nr, "s_per_rhs": round(sec / nr, 5), "seconds": round(sec, 3),
+               "iters_mean": round(float(np.mean(info["iters"])), 1),
+               "iters_max": max(info["iters"]), "true_resid_max": max(info["true_resid"]),
+               "converged": sum(info["converged"]), "fell_back": sum(info["fell_back"]),
+               "reliable_updates": info["reliable_updates"], "rc": info["rc"],
+               "peak_device_GB": round(info["peak_bytes"] / 1e9, 2),
+               "fp32_links_from_iter": info["link_switch_iter"],
+               "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
+        progress(f"  {label}: {res['s_per_rhs']} s/rhs, {res['iters_max']} iterations")
+        return res
 
-    solve("mixed_f16links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
-    solve("mixed_f32links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F32)
-    if st["plain"]:
-        solve("plain_f64", b, kind=hisq.HISQ_CG_F64)
+    out["mixed_f16links"] = solve("mixed_f16links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)
+    out["mixed_f32links"] = solve("mixed_f32links", b, kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F32)
+    if plain:
+        out["plain_f64"] = solve("plain_f64", b, kind=hisq.HISQ_CG_F64)
+    best = min(("mixed_f16links", hisq.HISQ_F16), ("mixed_f32links", hisq.HISQ_F32),
+               key=lambda kv: out[kv[0]]["seconds"])
+    out["mixed_best"] = best[0]
+    if plain:
+        out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out[best[0]]["seconds"], 3)
     # training pairs along plain-CG trajectories of Gaussian sources
     nsrc, nsnap = st["nsrc"], st["nsnap"]
     bs = torch.from_numpy(synth.sources(dims, nsrc, seed + 2)).to(dev)
@@ -269,64 +287,69 @@ def solver_study(args, torch, synth, hisq, pm):
     out["harvest"] = {"pairs": npairs.value, "sources": nsrc, "snapshot_every": st["snap"],
                       "seconds": round(time.perf_counter() - t, 2)}
     del bs
-    # Gram form N^dag N (Hermitian positive semi-definite) trained on the residual-norm loss
-    hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, 4, 8, seed))
-    hisq._check(lat.ctx, lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM))
-    hisq._check(lat.ctx, lib.hisq_nn_set_loss(lat.ctx, hisq.HISQ_NN_LOSS_RESIDUAL, mass))
-    # start from the best multiple of the identity for the residual loss on the training
-    # residuals, c = sum <r, M r> / sum ||M r||^2 (P = N^dag N scales as |W_out|^2)
+    # the best multiple of the identity for the residual loss on the training residuals,
+    # c = sum <r, M r> / sum ||M r||^2: the networks start there (P = c N for the direct form,
+    # c N^dag N for the Gram form, whose output scales as |W_out|^2)
     r32 = r[: min(16, npairs.value)].to(torch.complex64)
     mr = lat.apply_m(hisq.HISQ_F32, mass, r32)
     c = float(torch.sum((torch.conj(r32) * mr).real) / torch.sum(torch.abs(mr) ** 2))
     del r32, mr
-    nparam = lib.hisq_nn_num_params(lat.ctx)
-    w = (ctypes.c_double * (2 * nparam))()
-    hisq._check(lat.ctx, lib.hisq_nn_get_params(lat.ctx, w, 2 * nparam))
-    for k in range(2 * (nparam - 8), 2 * nparam):
-        w[k] *= c ** 0.5
-    hisq._check(lat.ctx, lib.hisq_nn_set_params(lat.ctx, w, 2 * nparam))
-    hist = (ctypes.c_double * epochs)()
-    batch, lr = 16, 1e-2
-    progress("train the network")
-    t = time.perf_counter()
-    hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
-                                           epochs, batch, lr, seed, hist))
-    out["training"] = {"form": "gram", "loss": "residual", "init_scale": round(c, 5), "epochs": epochs, "batch": batch,
-                       "lr": lr, "bf16": True, "seconds": round(time.perf_counter() - t, 2),
-                       "loss_first": round(hist[0], 5), "loss_last": round(hist[epochs - 1], 5)}
-    del r, y
     bf = b if st["n_fcg"] is None else b[:st["n_fcg"]].contiguous()
     nf = bf.shape[0]
-    # one preconditioner application on the FCG bundle (FP32 vectors), as inside the FCG
-    rv = bf.to(torch.complex64)
-    zv = torch.empty_like(rv)
-    for _ in range(2):
-        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, nf, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
-    e0, e1 = _events(torch)
-    e0.record()
-    for _ in range(5):
-        hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, nf, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
-    e1.record()
-    torch.cuda.synchronize()
-    out["network_apply_ms"] = {"n_rhs": nf, "ms": round(e0.elapsed_time(e1) / 5, 3)}
-    del rv, zv
-    # the faster mixed solver is the reference of the learned one (on the same bundle)
-    best = min(("mixed_f16links", hisq.HISQ_F16), ("mixed_f32links", hisq.HISQ_F32),
-               key=lambda kv: out[kv[0]]["seconds"])
+    ref_label = best[0] if nf == n else best[0] + "_fcg_bundle"
     if nf != n:
-        solve(best[0] + "_fcg_bundle", bf, kind=hisq.HISQ_CG_MIXED, link_prec=best[1])
-    # the flexible CG's inner operator with either link copy (the network reads the FP16 copy in
-    # both); the faster of the two is the learned solver's result
-    solve("fcg_learned_f16links", bf, kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F16)
-    solve("fcg_learned_f32links", bf, kind=hisq.HISQ_FCG_NN, link_prec=hisq.HISQ_F32)
-    fcg = min(("fcg_learned_f16links", "fcg_learned_f32links"), key=lambda k: out[k]["seconds"])
-    ref = out[best[0] if nf == n else best[0] + "_fcg_bundle"]
-    out["fcg_reference"] = best[0]
-    out["fcg_best"] = fcg
-    if st["plain"]:
-        out["speedup_mixed_vs_f64"] = round(out["plain_f64"]["seconds"] / out[best[0]]["seconds"], 3)
-    out["speedup_fcg_vs_mixed"] = round(ref["seconds"] / out[fcg]["seconds"], 3)
-    out["iteration_ratio_fcg_vs_mixed"] = round(out[fcg]["iters_mean"] / ref["iters_mean"], 3)
+        out[ref_label] = solve(ref_label, bf, kind=hisq.HISQ_CG_MIXED, link_prec=best[1])
+    out["learned"] = {}
+    for form, layers in variants:
+        key = f"{form}_L{layers}"
+        hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, layers, 8, seed))
+        hisq._check(lat.ctx, lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM if form == "gram"
+                                                  else hisq.HISQ_NN_FORM_DIRECT))
+        hisq._check(lat.ctx, lib.hisq_nn_set_loss(lat.ctx, hisq.HISQ_NN_LOSS_RESIDUAL, mass))
+        nparam = lib.hisq_nn_num_params(lat.ctx)
+        w = (ctypes.c_double * (2 * nparam))()
+        hisq._check(lat.ctx, lib.hisq_nn_get_params(lat.ctx, w, 2 * nparam))
+        scale = c ** 0.5 if form == "gram" else c
+        for k in range(2 * (nparam - 8), 2 * nparam):
+            w[k] *= scale
+        hisq._check(lat.ctx, lib.hisq_nn_set_params(lat.ctx, w, 2 * nparam))
+        hist = (ctypes.c_double * epochs)()
+        batch, lr = 16, 1e-2
+        progress(f"train the network {key}")
+        t = time.perf_counter()
+        hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
+                                               epochs, batch, lr, seed, hist))
+        v = {"form": form, "layers": layers, "channels": 8, "loss": "residual", "init_scale": round(c, 5),
+             "epochs": epochs, "batch": batch, "lr": lr, "bf16": True,
+             "training_s": round(time.perf_counter() - t, 2),
+             "loss_first": round(hist[0], 5), "loss_last": round(hist[epochs - 1], 5)}
+        # one preconditioner application on the FCG bundle (FP32 vectors), as inside the FCG
+        rv = bf.to(torch.complex64)
+        zv = torch.empty_like(rv)
+        for _ in range(2):
+            hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, nf, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
+        e0, e1 = _events(torch)
+        e0.record()
+        for _ in range(5):
+            hisq._check(lat.ctx, lib.hisq_nn_apply(lat.ctx, nf, hisq.HISQ_F32, hisq._ptr(rv), hisq._ptr(zv)))
+        e1.record()
+        torch.cuda.synchronize()
+        v["apply_ms"] = round(e0.elapsed_time(e1) / 5, 3)
+        del rv, zv
+        for lp in fcg_link_precs:
+            lab = "f16links" if lp == hisq.HISQ_F16 else "f32links"
+            v["fcg_" + lab] = solve(f"fcg_{key}_{lab}", bf, kind=hisq.HISQ_FCG_NN, link_prec=lp)
+        fbest = min((k for k in v if k.startswith("fcg_")), key=lambda k: v[k]["seconds"])
+        v["fcg_best"] = fbest
+        v["speedup_vs_mixed"] = round(out[ref_label]["seconds"] / v[fbest]["seconds"], 3)
+        v["iteration_ratio_vs_mixed"] = round(v[fbest]["iters_mean"] / out[ref_label]["iters_mean"], 3)
+        out["learned"][key] = v
+    lead = out["learned"][f"{variants[0][0]}_L{variants[0][1]}"]
+    out["fcg_learned"] = dict(lead[lead["fcg_best"]], network=f"{variants[0][0]}_L{variants[0][1]}",
+                              link_copy=lead["fcg_best"][4:])
+    out["fcg_reference"] = ref_label
+    out["speedup_fcg_vs_mixed"] = lead["speedup_vs_mixed"]
+    out["iteration_ratio_fcg_vs_mixed"] = lead["iteration_ratio_vs_mixed"]
     lat.close()
     return out
 
@@ -361,6 +384,131 @@ def volume_sweep(hisq, torch, synth, pm):
     return out
 
 
+# ---- CPU baseline: the FP64 oracle on the host's cores ----------------------------------------
+
+def _host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))  # the GPU machine's share of host cores is 16
+
+
+_CPU = {}
+
+
+def _cpu_init(dims, seed, nrhs):
+    # workers: numpy only, one thread each (the pool supplies the parallelism)
+    import synth
+    _CPU["dims"] = tuple(dims)
+    _CPU["links"] = synth.gauge_links(tuple(dims), seed)
+    _CPU["v"] = synth.sources(tuple(dims), nrhs, seed + 1)
+
+
+def _cpu_dslash(job):
+    """Whole-lattice Eq. 3 for rhs i, `reps` times; returns the seconds taken."""
+    import oracle
+    i, reps = job
+    fat, naik = _CPU["links"]
+    dims = _CPU["dims"]
+    full = oracle.embed(_CPU["v"][i], dims, 0) + oracle.embed(_CPU["v"][(i + 1) % len(_CPU["v"])], dims, 1)
+    t = time.perf_counter()
+    for _ in range(reps):
+        oracle.dslash_full(fat, naik, full, dims)
+    return time.perf_counter() - t
+
+
+def _cpu_cg(job):
+    """Oracle CG on one rhs: (iterations, seconds, true residual)."""
+    import oracle
+    i, mass, tol, max_iter = job
+    fat, naik = _CPU["links"]
+    dims = _CPU["dims"]
+    t = time.perf_counter()
+    x, it, res = oracle.cg(fat, naik, _CPU["v"][i:i + 1], dims, mass, tol, max_iter=max_iter, max_restarts=0)
+    return int(it[0]), time.perf_counter() - t, float(res[0])
+
+
+def cpu_baseline(dims, nrhs, gpu_cg_iters):
+    """The FP64 numpy oracle timed on the host's cores (a process per core, one thread each):
+    the whole-lattice Dslash of the benchmark step (Eq. 3 on both parities, 1146 flop per site and
+    rhs) over the benchmark's rhs, the oracle CG on the 8^4 workload solved in full, and the
+    oracle CG on the 32^3 x 8 workload per rhs, extrapolated from a timed sample of iterations to
+    the iteration count of the GPU's plain FP64 solve."""
+    import multiprocessing as mp
+    import platform
+    from concurrent.futures import ProcessPoolExecutor
+
+    import synth
+    from paper_1409_1510_amd import perfmodel as pm
+    cores = _host_cores()
+    env_threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_threads:
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    out = {"kind": "oracle", "cores": cores}
+    try:
+        # 1. whole-lattice Dslash, every worker on its own rhs, ~12 s of wall time
+        c1 = synth.WORKLOADS["c1"]
+        with ProcessPoolExecutor(cores, mp_context=ctx, initializer=_cpu_init,
+                                 initargs=(dims, synth.workload_seed("c1"), nrhs)) as ex:
+            probe = list(ex.map(_cpu_dslash, [(i, 1) for i in range(cores)]))
+            per = float(np.median(probe))
+            reps = max(1, int(12.0 / per))
+            t = time.perf_counter()
+            secs = list(ex.map(_cpu_dslash, [(i % nrhs, reps) for i in range(cores)]))
+            wall = time.perf_counter() - t
+        flops = cores * reps * pm.half_dslash_flops(int(np.prod(dims)) // 2, 1) * 2
+        out["value"] = round(flops / wall / 1e9, 3)
+        out["unit"] = "Gflop/s"
+        out["sample"] = (f"{cores * reps} whole-lattice FP64 oracle Dslash applications (Eq. 3 on both "
+                         f"parities, 1 rhs each, rhs of the {'x'.join(map(str, dims))} benchmark bundle) "
+                         f"in {cores} processes of one thread, {wall:.1f} s wall; the same work unit as "
+                         f"one benchmark step per rhs")
+        out["dslash_s_per_rhs"] = round(float(np.median(secs)) / reps, 4)
+        # 2. oracle CG: 8^4 solved in full; 32^3 x 8 sampled per rhs
+        c0, c2 = synth.WORKLOADS["c0"], synth.WORKLOADS["c2"]
+        with ProcessPoolExecutor(1, mp_context=ctx, initializer=_cpu_init,
+                                 initargs=(c0["dims"], synth.workload_seed("c0"), 1)) as ex0, \
+                ProcessPoolExecutor(2, mp_context=ctx, initializer=_cpu_init,
+                                    initargs=(c2["dims"], synth.workload_seed("c2"), 2)) as ex2:
+            f0 = ex0.submit(_cpu_cg, (0, c0["mass"], c0["tol"], 100000))
+            k = 8
+            f2 = [ex2.submit(_cpu_cg, (i, c2["mass"], c2["tol"], k)) for i in range(2)]
+            it0, s0, r0 = f0.result()
+            samples = [f.result() for f in f2]
+        out["cg_8x8x8x8"] = {"iters": it0, "seconds": round(s0, 3), "true_resid": r0, "tol": c0["tol"],
+                             "mass": c0["mass"], "s_per_rhs": round(s0, 3)}
+        # k iterations plus the initial and the final residual: k + 2 applications of M
+        s_it = float(np.mean([s for _, s, _ in samples])) / (k + 2)
+        c2_out = {"sample": f"{k} CG iterations on each of 2 rhs (one process each), plus the initial "
+                            "and final residual: s per iteration = time / (k + 2)",
+                  "s_per_iteration": round(s_it, 4), "mass": c2["mass"], "tol": c2["tol"]}
+        if gpu_cg_iters:
+            c2_out["gpu_plain_f64_iterations"] = gpu_cg_iters
+            c2_out["s_per_rhs_extrapolated"] = round(s_it * gpu_cg_iters, 1)
+        out["cg_32x32x32x8_per_rhs"] = c2_out
+        out["host"] = {"cores_used": cores, "os_cpu_count": os.cpu_count(), "machine": platform.machine(),
+                       "cpu_model": _cpu_model()}
+    finally:
+        for k, v in env_threads.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,10 +523,20 @@ def main():
                          "solver comparison at 48^3x12 / 64^3x16 (plain FP64, mixed, learned FCG)")
     ap.add_argument("--epochs", type=int, default=0,
                     help="training epochs of the solver study (0: 20)")
+    ap.add_argument("--nn-variants", default="",
+                    help="solver study: networks to train and solve with, as form:layers pairs, e.g. "
+                         "gram:4,gram:2,direct:4 (default gram:4)")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="leave out the 48^3x12 solver comparison of the default run")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one 256 MiB read + 256 MiB write elementwise "
                          "kernel (counter calibration), 100 ms of untimed steps with another "
                          "rhs_per_thread, then --steps FP32 Dslash steps")
+    ap.add_argument("--profile-dims", default="32,32,32,8",
+                    help="--profile: lattice extents (other than 32,32,32,8: tiled links, which the "
+                         "timing does not depend on)")
+    ap.add_argument("--profile-prec", default="f32", choices=["f32", "f16links"],
+                    help="--profile: FP32 links or FP16 link storage (FP32 vectors either way)")
     ap.add_argument("--profile-sweep", action="store_true",
                     help="short run for rocprofv3: the counter-calibration kernel, then for every "
                          "case of the n/precision sweep 50 ms of untimed steps, 1 warm-up step and "
@@ -439,7 +597,11 @@ def main():
         lat3.close()
         return
     if args.workload in ("c3", "c4"):
-        print(json.dumps(solver_study(args, torch, synth, hisq, pm)))
+        variants = None
+        if args.nn_variants:
+            variants = [(f.split(":")[0], int(f.split(":")[1])) for f in args.nn_variants.split(",")]
+        print(json.dumps(solver_study(args.workload, torch, synth, hisq, pm, epochs=args.epochs,
+                                      variants=variants)))
         return
     cfg = synth.WORKLOADS["c1"]
     dims, n = cfg["dims"], args.nrhs
@@ -482,17 +644,30 @@ def main():
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
+        del src, dst
+        pdims = tuple(int(d) for d in args.profile_dims.split(","))
+        prec = hisq.HISQ_F32 if args.profile_prec == "f32" else hisq.HISQ_F16
+        if pdims != dims:
+            lat.close()
+            fat_p, naik_p = synth.tiled_gauge_links(pdims, 7)
+            lat = hisq.Lattice(pdims, 0)
+            lat.load_links(fat_p, naik_p, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 18)
+            del fat_p, naik_p
+            v_e = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
+            v_o = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
+            w_e, w_o = torch.empty_like(v_e), torch.empty_like(v_o)
         # the sustained load runs the same kernel with another rhs_per_thread (another kernel
         # symbol), so that the trace's statistics of the timed kernel hold the timed launches only
-        tuned = hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)
-        hisq.hisq_set_launch(lat.ctx, hisq.HISQ_F32, n, (1 if tuned[0] > 1 else 2,) + tuned[1:])
-        sustain(torch, dslash_step(lat, hisq.HISQ_F32, v_e, v_o, w_e, w_o), RAMP_MS)
-        hisq.hisq_set_launch(lat.ctx, hisq.HISQ_F32, n, tuned)
-        _, ms_launch, _ = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
+        tuned = hisq.hisq_get_launch(lat.ctx, prec, n, 0)
+        hisq.hisq_set_launch(lat.ctx, prec, n, (1 if tuned[0] > 1 else 2,) + tuned[1:])
+        sustain(torch, dslash_step(lat, prec, v_e, v_o, w_e, w_o), RAMP_MS)
+        hisq.hisq_set_launch(lat.ctx, prec, n, tuned)
+        _, ms_launch, _ = dslash_step_timing(lat, hisq, torch, prec, v_e, v_o, w_e, w_o,
                                              args.steps, 0, isolated=False)
-        print(f"profile run done: {args.steps} steps, {n} rhs, lattice {dims}, launch "
-              f"{hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, n, 0)}, source {kernel_source_hash()}, "
-              f"region-timed average {ms_launch * 1e3:.1f} us per launch")
+        print(f"profile run done: {args.steps} steps, {n} rhs, lattice {pdims}, {args.profile_prec}, launch "
+              f"{tuple(hisq.hisq_get_launch(lat.ctx, prec, n, 0))}, source {kernel_source_hash()}, "
+              f"region-timed average {ms_launch * 1e3:.1f} us per launch, algorithmic bytes per launch "
+              f"{pm.half_dslash_bytes(lat.vh, n, prec, 18)}")
         lat.close()
         return
 
@@ -595,6 +770,29 @@ def main():
                         "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}
         cg["speedup_mixed_vs_f64"] = round(cg["plain_f64"]["seconds"] / min(cg["mixed_f16links"]["seconds"],
                                                                           cg["mixed_f32links"]["seconds"]), 3)
+        # repacking a bundle whose rhs finish at different iterations: 16 rhs, 12 of them started
+        # from a solution to 1e-5, against the same solve with the finished rhs only masked
+        b16 = torch.from_numpy(synth.sources(c2["dims"], 16, synth.workload_seed("c2") + 4)).to("cuda:0")
+        xa, _ = lat2.cg(c2["mass"], b16, tol=1e-5, max_iter=40000, kind=hisq.HISQ_CG_MIXED,
+                        link_prec=hisq.HISQ_F32)
+        x0 = xa.clone()
+        x0[12:] = 0
+        uneven = {"workload": "32x32x32x8, m=0.02, 16 complex Gaussian rhs, 12 of them started from a "
+                              "solution to 1e-5; mixed CG, FP16 links, tol 1e-8"}
+        for label, comp in (("repacked", True), ("masked", False)):
+            for rep in range(2):  # the first run tunes the launches of the smaller bundles
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                x, info = lat2.cg(c2["mass"], b16, tol=c2["tol"], max_iter=40000, kind=hisq.HISQ_CG_MIXED,
+                                  link_prec=hisq.HISQ_F16, x0=x0, compaction=comp)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t
+            uneven[label] = {"seconds": round(sec, 4), "iters_min": min(info["iters"]),
+                             "iters_max": max(info["iters"]), "repacks": info["compactions"],
+                             "true_resid_max": max(info["true_resid"]), "rc": info["rc"]}
+        uneven["speedup_repacked_vs_masked"] = round(uneven["masked"]["seconds"] / uneven["repacked"]["seconds"], 3)
+        cg["uneven_bundle"] = uneven
+        del b16, xa, x0, x
         result["cg"] = cg
         # the paper's multi-rhs CG figure, on other hardware (context, not a comparison target)
         result["paper_context"] = {
@@ -616,21 +814,19 @@ def main():
             "seconds": round(sec, 3), "s_per_vector": round(sec / nvec, 5)}
         lat2.close()
 
-    if not args.no_cpu:
-        import oracle
-        nthreads = 1
-        vs = v[:1]
+    if not args.no_c3 and not args.no_cg:
+        # the 48^3 x 12 solver comparison: plain FP64, mixed (FP16 and FP32 links) and the
+        # flexible CG with the learned preconditioner (its inner operator on the FP32 links)
         t = time.perf_counter()
-        reps = 0
-        while time.perf_counter() - t < 12.0 or reps < 1:
-            oracle.dslash_half(fat, naik, vs, dims, 1)
-            reps += 1
-        sec = time.perf_counter() - t
-        result["cpu_baseline"] = {
-            "value": round(reps * pm.half_dslash_flops(vh, 1) / sec / 1e9, 3), "unit": "Gflop/s",
-            "cores": nthreads, "kind": "oracle",
-            "sample": f"{reps} FP64 numpy-oracle half Dslash applications (1 rhs) on the same "
-                      f"32^3x8 links, {sec:.1f} s; single-threaded numpy"}
+        c3 = solver_study("c3", torch, synth, hisq, pm, fcg_link_precs=(hisq.HISQ_F32,))
+        c3["study_seconds"] = round(time.perf_counter() - t, 1)
+        result["cg_48x48x48x12"] = c3
+
+    if not args.no_cpu:
+        cg_iters = None
+        if "cg" in result:
+            cg_iters = result["cg"]["plain_f64"]["iters_max"]
+        result["cpu_baseline"] = cpu_baseline(dims, n, cg_iters)
     lat.close()
     print(json.dumps(result))
 

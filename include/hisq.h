@@ -172,6 +172,8 @@ typedef struct {
   int link_prec;      /* MIXED/FCG inner operator: HISQ_F32 or HISQ_F16                            */
   int use_x0;         /* 1: x holds the initial guess on entry; 0: start from x = 0                */
   int check_every;    /* host poll interval of the per-rhs residuals, iterations (0 = default 8)  */
+  int no_compaction;  /* F64/MIXED: 1 keeps every rhs in its bundle slot to the end; 0 (default)  */
+                      /*    repacks the bundle to its live rhs as rhs finish (see hisq_cg_mrhs)  */
 } hisq_cg_params;
 
 typedef struct {
@@ -183,14 +185,20 @@ typedef struct {
   int reliable_updates;/* FP64 residual replacements done                                        */
   long long dslash_site_rhs; /* sum over half-Dslash launches of (sites x active rhs)           */
   double seconds;      /* wall time of the solve                                                 */
-  size_t peak_bytes;   /* device workspace held by the context after the solve                   */
+  size_t peak_bytes;   /* most device memory the context held during the solve: link copies,     */
+                       /*    workspace, tuning scratch and network state (caller buffers excluded) */
   int link_switch_iter;/* MIXED with FP16 links: iteration at which the inner operator moved to   */
                        /*    the FP32 links (-1: never); see hisq_cg_mrhs                        */
+  int compactions;     /* F64/MIXED: times the bundle was repacked to its live rhs (see below)   */
 } hisq_cg_stats;
 
 /* Solve M x_i = b_i (M = m^2 - D_eo D_oe on even sites) for n right-hand sides at once; each
  * rhs has its own CG scalars and stops individually (Section 2: the remaining linear algebra
- * is kept separate per rhs so converged rhs can stop).
+ * is kept separate per rhs so converged rhs can stop).  HISQ_CG_F64 and HISQ_CG_MIXED repack the
+ * bundle once a quarter of its slots have finished: finished rhs leave (their solution is written
+ * to x), the live ones move to the front, and every later launch works on the smaller bundle
+ * with the launch configuration of its size (p->no_compaction = 1 turns this off).  A rhs's
+ * result does not depend on the repacking or on the other rhs of the bundle.
  *   b : device [n][3][V/2] complex128, even sites.   x : device [n][3][V/2] complex128.
  *   HISQ_CG_F64   : FP64 throughout.
  *   HISQ_CG_MIXED : FP32 Dslash/BLAS body (links p->link_prec), FP64 solution accumulation, FP64
@@ -198,7 +206,10 @@ typedef struct {
  *                   With FP16 links the inner operator moves to the FP32 links (when loaded)
  *                   once the FP16 error dominates: two replacements in a row where the true
  *                   residual exceeds the iterated one by more than 2x in norm while the relative
- *                   residual is still above 1e-5, or a stalled true residual.
+ *                   residual is still above 1e-5, a stalled true residual, or a falling
+ *                   convergence rate (the mean log true residual of the live rhs falls, over the
+ *                   last 8 replacements, at less than 0.8 times the best such rate of the solve,
+ *                   while it is still 100x above tol).
  *   HISQ_FCG_NN   : flexible CG preconditioned by the network of hisq_nn_init/hisq_nn_train
  *                   (Notay's FCG with truncation 1, complex step sizes; FP32 body with
  *                   p->link_prec links, FP64 reliable updates); a rhs whose preconditioned step

@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "cg_state.hpp"
@@ -26,6 +28,65 @@ int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, cons
                  hisq_cg_stats *st, CGState *S, CGState *hS, double *partial);
 
 namespace {
+
+bool cg_trace() {
+  static const bool on = [] {
+    const char *e = getenv("HISQ_CG_TRACE");
+    return e && atoi(e) != 0;
+  }();
+  return on;
+}
+
+// What the final residual needs of a rhs that left the bundle.
+struct SlotRecord {
+  int iters = 0, replacements = 0, status = 0;
+  double bnorm2 = 0.0;
+};
+
+// Slot src[j] of the state moves to slot j for j < m; the slots from m on are cleared.
+void permute_state(CGState &s, const int *src, int m) {
+  const CGState o = s;
+  for (int j = 0; j < HISQ_MAX_RHS; ++j) {
+    if (j >= m) {
+      s.active[j] = s.hit[j] = s.sel[j] = s.fin[j] = 0;
+      continue;
+    }
+    const int k = src[j];
+    s.rho[j] = o.rho[k];
+    s.pq[j] = o.pq[k];
+    s.alpha[j] = o.alpha[k];
+    s.beta[j] = o.beta[k];
+    s.bnorm2[j] = o.bnorm2[k];
+    s.rr[j] = o.rr[k];
+    s.rr_true[j] = o.rr_true[k];
+    s.drift[j] = o.drift[k];
+    for (int c = 0; c < 2; ++c) {
+      s.calpha[2 * j + c] = o.calpha[2 * k + c];
+      s.cbeta[2 * j + c] = o.cbeta[2 * k + c];
+    }
+    s.active[j] = o.active[k];
+    s.hit[j] = o.hit[k];
+    s.sel[j] = o.sel[k];
+    s.fin[j] = o.fin[k];
+    s.status[j] = o.status[k];
+    s.iters[j] = o.iters[k];
+    s.replacements[j] = o.replacements[k];
+  }
+}
+
+// The state of rhs 0..n-1 in the caller's order from the records of the rhs that left the bundle,
+// ready for the final residual of every rhs.
+void restore_state(CGState &s, const SlotRecord *done, int n) {
+  for (int i = 0; i < HISQ_MAX_RHS; ++i) {
+    s.active[i] = s.hit[i] = s.sel[i] = 0;
+    s.fin[i] = i < n;
+    if (i >= n) continue;
+    s.iters[i] = done[i].iters;
+    s.replacements[i] = done[i].replacements;
+    s.status[i] = done[i].status;
+    s.bnorm2[i] = done[i].bnorm2;
+  }
+}
 
 struct Vecs {
   void *r = nullptr, *p = nullptr, *q = nullptr, *t = nullptr, *xh = nullptr;
@@ -83,7 +144,7 @@ int cg_finish(hisq_ctx *ctx, double mass, int n, const void *b, void *x, double 
   }
   if (st) {
     st->dslash_site_rhs = site_rhs;
-    st->peak_bytes = ws_total(ctx);
+    st->peak_bytes = ctx->dev_peak;
   }
   *all_conv = ok;
   return HISQ_OK;
@@ -145,22 +206,108 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
     last_rep[i] = 0;
   }
   int switch_iter = -1;
+  // FP16-link rate test: (iteration, mean log relative true residual of the live rhs) at the
+  // periodic replacements, and the best rate so far
+  int rate_it[kRateWindow + 1];
+  double rate_l[kRateWindow + 1];
+  int rate_len = 0, rate_reps = 0, rate_live = -1;
+  double rate_best = 0.0;
+
+  // Compaction of the bundle (converged rhs stop costing work, Section 2): the iteration runs on
+  // ns slots, slot k holding rhs map[k].  Once a quarter of the slots have finished, the finished
+  // ones hand their solution to the caller's x and the live ones move to the front, so every
+  // kernel runs on a bundle of live rhs only (with the launch configuration tuned for its size).
+  // Until the first repack the slots are the caller's rhs and xw, bw are the caller's x, b; from
+  // then on they are slot-ordered copies in the workspace.  Each rhs's arithmetic does not depend
+  // on its slot or on the bundle size, so a repack does not change any result.
+  const bool can_compact = !prm->no_compaction && !snap_x;
+  int map[HISQ_MAX_RHS];
+  for (int i = 0; i < n; ++i) map[i] = i;
+  int ns = n;
+  void *xw = x;
+  const void *bw = b;
+  SlotRecord done[HISQ_MAX_RHS];
+  int compactions = 0;
+  const size_t xb1 = size_t(3) * g.vh * 16;                // one FP64 rhs
+  const size_t vb1 = size_t(3) * g.vh * cplx_bytes(body);  // one rhs of a body vector
+  auto slot_copy = [&](void *base, size_t bytes, int from, int to) -> int {
+    char *c = static_cast<char *>(base);
+    HIPCHK(ctx, hipMemcpyAsync(c + size_t(to) * bytes, c + size_t(from) * bytes, bytes,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    return HISQ_OK;
+  };
+  auto hand_back = [&](int k) -> int {  // slot k's solution to the caller's x, its statistics kept
+    HIPCHK(ctx, hipMemcpyAsync(static_cast<char *>(x) + size_t(map[k]) * xb1,
+                               static_cast<const char *>(xw) + size_t(k) * xb1, xb1,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    done[map[k]] = SlotRecord{hS->iters[k], hS->replacements[k], hS->status[k], hS->bnorm2[k]};
+    return HISQ_OK;
+  };
+  auto repack = [&]() -> int {
+    if (xw == x) {  // first repack: slot-ordered copies of x and b
+      void *xc, *bc;
+      RETCHK(ws_get(ctx, WS_CMPX, size_t(n) * xb1, &xc));
+      RETCHK(ws_get(ctx, WS_CMPB, size_t(n) * xb1, &bc));
+      HIPCHK(ctx, hipMemcpyAsync(xc, x, size_t(ns) * xb1, hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(ctx, hipMemcpyAsync(bc, b, size_t(ns) * xb1, hipMemcpyDeviceToDevice, ctx->stream));
+      xw = xc;
+      bw = bc;
+    }
+    if (mixed) {  // finished slots: x += xhat (live slots keep their xhat, which moves with them)
+      for (int k = 0; k < HISQ_MAX_RHS; ++k) hS->sel[k] = k < ns && !hS->active[k];
+      HIPCHK(ctx, hipMemcpyAsync(S, hS, sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
+      RETCHK(cg_accum_x(ctx, xw, v.xh, S->sel, ns));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // the upload has read hS before it changes
+    }
+    int src[HISQ_MAX_RHS], m = 0;
+    for (int k = 0; k < ns; ++k) {
+      if (hS->active[k])
+        src[m++] = k;
+      else
+        RETCHK(hand_back(k));
+    }
+    // live slots to the front, in order (slot src[j] >= j, so the in-place moves never overwrite
+    // a slot that is still to be moved)
+    int newmap[HISQ_MAX_RHS];
+    for (int j = 0; j < m; ++j) {
+      const int k = src[j];
+      newmap[j] = map[k];
+      best[j] = best[k];
+      stale[j] = stale[k];
+      drifting[j] = drifting[k];
+      last_rep[j] = last_rep[k];
+      if (k == j) continue;
+      RETCHK(slot_copy(v.r, vb1, k, j));
+      RETCHK(slot_copy(v.p, vb1, k, j));
+      if (mixed) RETCHK(slot_copy(v.xh, vb1, k, j));
+      RETCHK(slot_copy(xw, xb1, k, j));
+      RETCHK(slot_copy(const_cast<void *>(bw), xb1, k, j));
+    }
+    for (int j = 0; j < m; ++j) map[j] = newmap[j];
+    permute_state(*hS, src, m);
+    HIPCHK(ctx, hipMemcpyAsync(S, hS, sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // hS is read and written by the host again
+    ns = m;
+    ++compactions;
+    return HISQ_OK;
+  };
 
   auto reliable = [&](int all) -> int {
-    RETCHK(cg_select(ctx, S, n, all));
+    RETCHK(cg_select(ctx, S, ns, all));
     if (mixed) {
-      RETCHK(cg_accum_x(ctx, x, v.xh, S->sel, n));
-      RETCHK(apply_m64(ctx, mass, n, x, v.t64, v.mx64, S->sel));
-      RETCHK(cg_replace_r(ctx, body, b, v.mx64, v.r, nullptr, S, S->sel, n, partial));
+      RETCHK(cg_accum_x(ctx, xw, v.xh, S->sel, ns));
+      RETCHK(apply_m64(ctx, mass, ns, xw, v.t64, v.mx64, S->sel));
+      RETCHK(cg_replace_r(ctx, body, bw, v.mx64, v.r, nullptr, S, S->sel, ns, partial));
     } else {  // verify, restart from x if the true residual misses tol
-      RETCHK(apply_m64(ctx, mass, n, x, v.t, v.q, S->sel));
-      RETCHK(cg_replace_r(ctx, body, b, v.q, v.r, v.p, S, S->sel, n, partial));
+      RETCHK(apply_m64(ctx, mass, ns, xw, v.t, v.q, S->sel));
+      RETCHK(cg_replace_r(ctx, body, bw, v.q, v.r, v.p, S, S->sel, ns, partial));
     }
-    RETCHK(cg_reduce_true(ctx, partial, S, n, tol2, 0));
+    RETCHK(cg_reduce_true(ctx, partial, S, ns, tol2, 0));
     return HISQ_OK;
   };
 
   int it = 0;
+  int trace_rep = 0;
   int nactive = 0;
   for (int i = 0; i < n; ++i) nactive += hS->active[i];
   int reps = 0;
@@ -177,11 +324,11 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
   RETCHK(snapshot());
   while (nactive > 0 && it < prm->max_iter) {
     int nblk_d = 0;
-    RETCHK(cg_apply_op(ctx, op_prec, mass, n, v.p, v.t, v.q, partial, &nblk_d, S->active));
-    RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, n));
-    RETCHK(cg_update_r(ctx, body, v.r, v.q, S, n, partial));
-    RETCHK(cg_reduce_beta(ctx, partial, S, n, tol2));
-    RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : x, v.r, v.p, S, n));
+    RETCHK(cg_apply_op(ctx, op_prec, mass, ns, v.p, v.t, v.q, partial, &nblk_d, S->active));
+    RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, ns));
+    RETCHK(cg_update_r(ctx, body, v.r, v.q, S, ns, partial));
+    RETCHK(cg_reduce_beta(ctx, partial, S, ns, tol2));
+    RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns));
     ++it;
     RETCHK(snapshot());
     if (mixed && it % reliable_every == 0) {
@@ -191,21 +338,30 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
     if (it % check_every == 0 || it == prm->max_iter) {
       RETCHK(poll(ctx, S, hS));
       bool any_hit = false;
-      for (int i = 0; i < n; ++i) any_hit = any_hit || (hS->active[i] && hS->hit[i]);
+      for (int i = 0; i < ns; ++i) any_hit = any_hit || (hS->active[i] && hS->hit[i]);
       if (any_hit) {
         RETCHK(reliable(0));
         ++reps;
         RETCHK(poll(ctx, S, hS));
       }
       nactive = 0;
-      for (int i = 0; i < n; ++i) nactive += hS->active[i];
+      for (int i = 0; i < ns; ++i) nactive += hS->active[i];
+      if (cg_trace() && hS->replacements[0] != trace_rep) {
+        // diagnostic (HISQ_CG_TRACE=1): the true residual and the true / iterated residual ratio
+        // of slot 0 at each of its residual replacements
+        trace_rep = hS->replacements[0];
+        fprintf(stderr, "hisq cg trace: it %d links %s rhs0 true %.4e drift %.4f active %d\n", it,
+                op_prec == HISQ_F16 ? "f16" : (op_prec == HISQ_F32 ? "f32" : "f64"),
+                std::sqrt(hS->rr_true[0] / (hS->bnorm2[0] > 0 ? hS->bnorm2[0] : 1.0)),
+                std::sqrt(hS->drift[0]), nactive);
+      }
       if (mixed && op_prec == HISQ_F16 && ctx->links[HISQ_F32].base) {
         // FP16-link error dominating (the true residual drifts away from the iterated one well
         // above the FP32 floor) or a stalled true residual: the inner operator moves to the FP32
         // links for the rest of the solve (the FP16 rounding of ~5e-4 can slow CG a lot on
         // ill-conditioned systems).
         bool to_f32 = false;
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; i < ns; ++i) {
           if (!hS->active[i] || hS->replacements[i] == last_rep[i]) continue;
           last_rep[i] = hS->replacements[i];
           if (hS->drift[i] > kDriftRatio && hS->rr_true[i] > kDriftFloor2 * hS->bnorm2[i]) {
@@ -220,15 +376,49 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
             to_f32 = true;
           }
         }
+        if (reps != rate_reps && nactive > 0) {  // a periodic replacement since the last poll
+          rate_reps = reps;
+          double l = 0.0;
+          for (int i = 0; i < ns; ++i)
+            if (hS->active[i]) l += 0.5 * std::log(hS->rr_true[i] / hS->bnorm2[i]);
+          l /= nactive;
+          if (nactive != rate_live) rate_len = 0;  // the set of live rhs changed: start again
+          rate_live = nactive;
+          if (rate_len == kRateWindow + 1) {
+            for (int k = 0; k < kRateWindow; ++k) {
+              rate_it[k] = rate_it[k + 1];
+              rate_l[k] = rate_l[k + 1];
+            }
+            --rate_len;
+          }
+          rate_it[rate_len] = it;
+          rate_l[rate_len] = l;
+          ++rate_len;
+          if (rate_len == kRateWindow + 1) {
+            const double rate = (rate_l[0] - rate_l[kRateWindow]) / double(rate_it[kRateWindow] - rate_it[0]);
+            rate_best = std::max(rate_best, rate);
+            if (rate < kRateFrac * rate_best && l > std::log(kRateNearTol * prm->tol)) to_f32 = true;
+          }
+        }
         if (to_f32) {
           op_prec = HISQ_F32;
           switch_iter = it;
         }
       }
+      if (can_compact && nactive > 0 && ns - nactive >= std::max(1, ns / 4)) RETCHK(repack());
     }
   }
   if (mixed) {  // fold the last FP32 correction of every rhs into x
-    RETCHK(cg_accum_x(ctx, x, v.xh, S->fin, n));
+    RETCHK(cg_accum_x(ctx, xw, v.xh, S->fin, ns));
+  }
+  if (xw != x) {
+    // compacted: the remaining slots' solutions to the caller's x, and the per-rhs state in the
+    // caller's order for the final residual
+    RETCHK(poll(ctx, S, hS));
+    for (int k = 0; k < ns; ++k) RETCHK(hand_back(k));
+    restore_state(*hS, done, n);
+    HIPCHK(ctx, hipMemcpyAsync(S, hS, sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   }
   if (n_taken) *n_taken = taken;
   bool ok = false;
@@ -237,6 +427,7 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
     st->total_iters = it;
     st->reliable_updates = reps;
     st->link_switch_iter = switch_iter;
+    st->compactions = compactions;
     if (st->fell_back)
       for (int i = 0; i < n; ++i) st->fell_back[i] = 0;
   }
@@ -265,7 +456,11 @@ extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, vo
   if (prm->kind != HISQ_CG_F64 && !ctx->links[prm->link_prec].base)
     return set_err(ctx, HISQ_ERR_STATE, "hisq_cg_mrhs: link copy of the requested precision missing");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  if (st) st->link_switch_iter = -1;
+  if (st) {
+    st->link_switch_iter = -1;
+    st->compactions = 0;
+  }
+  ctx->dev_peak = ctx->dev_bytes;  // peak_bytes: the most the context holds during this solve
   auto t0 = std::chrono::steady_clock::now();
   void *sp, *pp, *hp;
   RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));

@@ -18,6 +18,17 @@ constexpr int kStallUpdates = 6;
 constexpr double kDriftRatio = 4.0;
 constexpr double kDriftFloor2 = 1e-10;
 constexpr int kDriftUpdates = 2;
+// FP16-link rate test of the mixed solver: on ill-conditioned systems the FP16 rounding of the
+// links slows CG more and more as the residual falls while the true and the iterated residual
+// stay together (measured on 48^3 x 12 at m = 0.01: the true residual falls 3.6x per 500
+// iterations at its best and 1.3x at the end, against a steady 3.8x with FP32 links; on 32^3 x 8
+// at m = 0.02 it stays within 0.96 of its best).  The convergence rate, d(mean over the live rhs
+// of log ||b - Mx|| / ||b||) per iteration over the last kRateWindow periodic residual
+// replacements, below kRateFrac of the best such rate of the solve moves the operator to the
+// FP32 links, unless the residual is already within kRateNearTol of tol.
+constexpr int kRateWindow = 8;
+constexpr double kRateFrac = 0.8;
+constexpr double kRateNearTol = 100.0;
 
 struct CGState {
   double rho[HISQ_MAX_RHS];      // <r, r> of the iterated residual (or <z, r> for FCG)

@@ -1,4 +1,5 @@
 // Context lifecycle, errors, workspace and link loading of libhisq.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,34 +24,44 @@ int set_err(hisq_ctx *ctx, int code, const char *fmt, ...) {
 bool prec_valid(int prec) { return prec == HISQ_F64 || prec == HISQ_F32 || prec == HISQ_F16; }
 size_t cplx_bytes(int prec) { return prec == HISQ_F64 ? 16 : 8; }
 
+int dev_alloc(hisq_ctx *ctx, void **p, size_t bytes, const char *what) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return set_err(ctx, HISQ_ERR_OOM, "%s: device allocation of %zu bytes failed: %s", what, bytes,
+                   hipGetErrorString(e));
+  }
+  ctx->dev_bytes += bytes;
+  if (ctx->dev_bytes > ctx->dev_peak) ctx->dev_peak = ctx->dev_bytes;
+  return HISQ_OK;
+}
+
+void dev_free(hisq_ctx *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->dev_bytes -= std::min(bytes, ctx->dev_bytes);
+}
+
 int ws_get(hisq_ctx *ctx, int slot, size_t bytes, void **out) {
   if (bytes == 0) bytes = 256;
   if (ctx->ws_bytes[slot] < bytes) {
     if (ctx->ws[slot]) {
       HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-      HIPCHK(ctx, hipFree(ctx->ws[slot]));
-      ctx->ws[slot] = nullptr;
-      ctx->ws_bytes[slot] = 0;
+      ws_release(ctx, slot);
     }
     size_t want = (bytes + 4095) & ~size_t(4095);
-    hipError_t e = hipMalloc(&ctx->ws[slot], want);
-    if (e != hipSuccess) {
-      ctx->ws[slot] = nullptr;
-      (void)hipGetLastError();
-      return set_err(ctx, HISQ_ERR_OOM, "workspace allocation of %zu bytes failed: %s", want,
-                     hipGetErrorString(e));
-    }
+    RETCHK(dev_alloc(ctx, &ctx->ws[slot], want, "workspace"));
     ctx->ws_bytes[slot] = want;
   }
   *out = ctx->ws[slot];
   return HISQ_OK;
 }
 
-size_t ws_total(const hisq_ctx *ctx) {
-  size_t s = 0;
-  for (int i = 0; i < WS_COUNT; ++i) s += ctx->ws_bytes[i];
-  for (int p = 0; p < 3; ++p) s += ctx->links[p].bytes;
-  return s;
+void ws_release(hisq_ctx *ctx, int slot) {
+  dev_free(ctx, ctx->ws[slot], ctx->ws_bytes[slot]);
+  ctx->ws[slot] = nullptr;
+  ctx->ws_bytes[slot] = 0;
 }
 
 int pinned_get(hisq_ctx *ctx, size_t bytes, void **out) {
@@ -70,7 +81,7 @@ int pinned_get(hisq_ctx *ctx, size_t bytes, void **out) {
 
 static void free_links(hisq_ctx *ctx) {
   for (auto &l : ctx->links) {
-    if (l.base) (void)hipFree(l.base);
+    dev_free(ctx, l.base, l.bytes);
     l = LinkCopy{};
   }
   ctx->links_loaded = false;
@@ -128,8 +139,7 @@ int hisq_destroy(hisq_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   free_links(ctx);
-  for (int i = 0; i < WS_COUNT; ++i)
-    if (ctx->ws[i]) (void)hipFree(ctx->ws[i]);
+  for (int i = 0; i < WS_COUNT; ++i) ws_release(ctx, i);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   nn_free_state(ctx);
   delete ctx;
@@ -211,13 +221,10 @@ extern "C" int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *n
     int recon = prec == HISQ_F64 ? 18 : naik_recon;
     size_t per_par = size_t(link_planes_total(recon)) * g.vh * link_elem_bytes(prec);
     LinkCopy &l = ctx->links[prec];
-    hipError_t e = hipMalloc(&l.base, 2 * per_par);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      l.base = nullptr;
+    int rc_alloc = dev_alloc(ctx, &l.base, 2 * per_par, "hisq_load_links");
+    if (rc_alloc != HISQ_OK) {
       free_links(ctx);
-      return set_err(ctx, HISQ_ERR_OOM, "hisq_load_links: allocation of %zu bytes failed",
-                     2 * per_par);
+      return rc_alloc;
     }
     l.bytes = 2 * per_par;
     l.recon = recon;
@@ -241,11 +248,7 @@ extern "C" int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *n
     }
   }
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-  if (ctx->ws[WS_LINKSTAGE]) {  // the staging copy is only needed while packing
-    HIPCHK(ctx, hipFree(ctx->ws[WS_LINKSTAGE]));
-    ctx->ws[WS_LINKSTAGE] = nullptr;
-    ctx->ws_bytes[WS_LINKSTAGE] = 0;
-  }
+  ws_release(ctx, WS_LINKSTAGE);  // the staging copy is only needed while packing
   ctx->naik_recon = naik_recon;
   ctx->links_loaded = true;
   return HISQ_OK;

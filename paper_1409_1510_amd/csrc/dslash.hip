@@ -59,12 +59,14 @@ int max_tiles(const hisq_launch &c) {
 bool fits_n(const hisq_launch &c, int n) {
   return (n + c.rhs_per_thread - 1) / c.rhs_per_thread <= max_tiles(c);
 }
-// the LDS forms address a rhs tile (2 rhs_per_thread rhs in the 32-site form) with 32-bit byte
-// offsets
+// every form addresses a rhs tile with 32-bit offsets: the LDS forms in bytes (a tile of
+// rhs_per_thread rhs, 2 rhs_per_thread in the 32-site form), the register-tile form in complex
+// elements
 bool fits_lattice(const hisq_launch &c, const Geometry &g, int prec) {
   const size_t elem = prec == HISQ_F64 ? 16 : 8;
   const size_t tile = size_t(c.rhs_per_thread) * (c.sites_per_block == 32 ? 2 : 1);
-  return !c.lds_links || tile * 3 * size_t(g.vh) * elem < (size_t(1) << 32);
+  const size_t span = tile * 3 * size_t(g.vh) * (c.lds_links ? elem : 1);
+  return span < (size_t(1) << 32);
 }
 
 int next_pow2(int n) {
@@ -73,12 +75,15 @@ int next_pow2(int n) {
   return p;
 }
 
-// Heuristic used until a configuration is tuned or forced.
-hisq_launch heuristic(int prec, int n, bool epi) {
+// Heuristic used until a configuration is tuned or forced (the largest register tile up to 4 or
+// 8 rhs whose offsets fit in 32 bits on this lattice).
+hisq_launch heuristic(const Geometry &g, int prec, int n, bool epi) {
   int cap = (prec == HISQ_F64 || epi) ? 4 : 8;
   int rt = 1;
   while (rt * 2 <= cap && rt * 2 <= n) rt *= 2;
-  return hisq_launch{rt, 256, 0, 0, 0};
+  hisq_launch c{rt, 256, 0, 0, 0};
+  while (c.rhs_per_thread > 1 && !fits_lattice(c, g, prec)) c.rhs_per_thread /= 2;
+  return c;
 }
 
 struct Geo {
@@ -135,7 +140,8 @@ int run(hisq_ctx *ctx, int out_parity, int prec, int n, const void *in, void *ou
   if (!fits_n(c, n))
     return set_err(ctx, HISQ_ERR_ARG, "this Dslash form holds at most %d rhs tiles (n = %d)", max_tiles(c), n);
   if (!fits_lattice(c, ctx->g, prec))
-    return set_err(ctx, HISQ_ERR_ARG, "the LDS Dslash forms need rhs_per_thread * 3 * V/2 * (vector element size) < 4 GiB");
+    return set_err(ctx, HISQ_ERR_ARG, "rhs_per_thread too large for this lattice: a rhs tile must span less "
+                   "than 2^32 bytes (LDS forms) or complex elements (register-tile form)");
   if (c.xcd_map && geo.xmap != c.xcd_map) return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
   Args a{l.par[out_parity], in, out, ctx->g, out_parity, n, geo.ntiles, geo.ngroups, geo.nsblk,
          mass2, pvec, partial, active, geo.xmap, geo.zmap_bps, geo.zmap_zr,
@@ -170,7 +176,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   hipEvent_t e0, e1;
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
-  hisq_launch best = heuristic(prec, n, epi);
+  hisq_launch best = heuristic(g, prec, n, epi);
   float best_ms = 1e30f;
   const int rts[] = {1, 2, 4, 8, 16};
   int rc = HISQ_OK;
@@ -220,11 +226,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  for (int slot : {WS_TUNE0, WS_TUNE1, WS_TUNE2}) {  // tuning scratch is not kept
-    (void)hipFree(ctx->ws[slot]);
-    ctx->ws[slot] = nullptr;
-    ctx->ws_bytes[slot] = 0;
-  }
+  for (int slot : {WS_TUNE0, WS_TUNE1, WS_TUNE2}) ws_release(ctx, slot);  // tuning scratch is not kept
   if (rc != HISQ_OK) return rc;
   TuneEntry &t = ctx->tune[prec][n][epi ? 1 : 0];
   t.cfg = best;
@@ -241,7 +243,7 @@ int config_for(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *c) {
     if (autotune_enabled()) {
       RETCHK(tune(ctx, prec, n, epi, nullptr, nullptr));
     } else {
-      t.cfg = heuristic(prec, n, epi);
+      t.cfg = heuristic(ctx->g, prec, n, epi);
       t.state = TuneEntry::HEURISTIC;
     }
   }
@@ -293,7 +295,8 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
                      max_tiles(c), n);
     if (!fits_lattice(c, ctx->g, prec))
       return set_err(ctx, HISQ_ERR_ARG,
-                     "hisq_set_launch: the LDS forms need rhs_per_thread * 3 * V/2 * (vector element size) < 4 GiB");
+                     "hisq_set_launch: rhs_per_thread too large for this lattice (a rhs tile must span less "
+                     "than 2^32 bytes in the LDS forms, 2^32 complex elements in the register-tile form)");
     t.cfg = c;
     t.state = TuneEntry::FORCED;
   }
@@ -305,7 +308,7 @@ extern "C" int hisq_get_launch(hisq_ctx *ctx, int prec, int n, int fused_m, hisq
   if (!cfg || !prec_valid(prec) || n < 1 || n > HISQ_MAX_RHS)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_get_launch: bad argument");
   const TuneEntry &t = ctx->tune[prec][n][fused_m ? 1 : 0];
-  *cfg = t.state == TuneEntry::NONE ? heuristic(prec, n, fused_m != 0) : t.cfg;
+  *cfg = t.state == TuneEntry::NONE ? heuristic(ctx->g, prec, n, fused_m != 0) : t.cfg;
   return HISQ_OK;
 }
 

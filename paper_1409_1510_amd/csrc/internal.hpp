@@ -52,6 +52,7 @@ enum WsSlot {
   WS_NN0, WS_NN1, WS_NN2, WS_NN3, WS_NN4, WS_NN5, WS_NN6, WS_NN7,
   WS_TUNE0, WS_TUNE1, WS_TUNE2,  // launch-configuration tuning scratch (freed after tuning)
   WS_TR0, WS_TR1, WS_TR2,        // trace estimator: noise bundle, solutions, dot results
+  WS_CMPX, WS_CMPB,              // slot-ordered solution and source of a compacted CG bundle
   WS_COUNT
 };
 
@@ -80,6 +81,8 @@ struct hisq_ctx {
   void *pinned = nullptr;            // pinned host mirror of per-rhs residuals
   size_t pinned_bytes = 0;
   NNState *nn = nullptr;
+  size_t dev_bytes = 0;              // device memory the context holds now (dev_alloc / dev_free)
+  size_t dev_peak = 0;               // largest dev_bytes since the last reset (a solve resets it)
 };
 
 int set_err(hisq_ctx *ctx, int code, const char *fmt, ...);
@@ -104,9 +107,15 @@ int set_err(hisq_ctx *ctx, int code, const char *fmt, ...);
     if (rc_ != HISQ_OK) return rc_;                                                           \
   } while (0)
 
+// Every device allocation of the context goes through these two, which keep dev_bytes and its
+// running peak dev_peak (links, workspace slots, tuning scratch, network state).
+int dev_alloc(hisq_ctx *ctx, void **p, size_t bytes, const char *what);
+void dev_free(hisq_ctx *ctx, void *p, size_t bytes);
+
 // Grow-only device workspace slot.
 int ws_get(hisq_ctx *ctx, int slot, size_t bytes, void **out);
-size_t ws_total(const hisq_ctx *ctx);
+// Release a workspace slot (tuning scratch, link staging).
+void ws_release(hisq_ctx *ctx, int slot);
 int pinned_get(hisq_ctx *ctx, size_t bytes, void **out);
 
 // ---- kernels' host launchers (each enqueues on ctx->stream and checks the launch) ----

@@ -868,9 +868,13 @@ struct NNState {
 void nn_free_state(hisq_ctx *ctx) {
   NNState *s = ctx->nn;
   if (!s) return;
-  for (void *p : {static_cast<void *>(s->theta), static_cast<void *>(s->adam_m),
-                  static_cast<void *>(s->adam_v), static_cast<void *>(s->grad), s->act, s->scratch})
-    if (p) (void)hipFree(p);
+  const size_t nreal = size_t(2) * s->nparam;
+  dev_free(ctx, s->theta, nreal * sizeof(float));
+  dev_free(ctx, s->adam_m, nreal * sizeof(float));
+  dev_free(ctx, s->adam_v, nreal * sizeof(float));
+  dev_free(ctx, s->grad, nreal * sizeof(double));
+  dev_free(ctx, s->act, s->act_bytes);
+  dev_free(ctx, s->scratch, s->scratch_bytes);
   delete s;
   ctx->nn = nullptr;
 }
@@ -883,16 +887,12 @@ int grow(hisq_ctx *ctx, void **p, size_t *cur, size_t bytes) {
   if (*cur >= bytes) return HISQ_OK;
   if (*p) {
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    HIPCHK(ctx, hipFree(*p));
+    dev_free(ctx, *p, *cur);
     *p = nullptr;
     *cur = 0;
   }
   bytes = (bytes + 4095) & ~size_t(4095);
-  if (hipMalloc(p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return set_err(ctx, HISQ_ERR_OOM, "network workspace allocation of %zu bytes failed", bytes);
-  }
+  RETCHK(dev_alloc(ctx, p, bytes, "network workspace"));
   *cur = bytes;
   return HISQ_OK;
 }
@@ -1298,13 +1298,13 @@ extern "C" int hisq_nn_init(hisq_ctx *ctx, int layers, int channels, unsigned lo
   s->off_out = k;
   const size_t nreal = size_t(2) * s->nparam;
   void *p;
-  if (hipMalloc(&p, nreal * sizeof(float)) != hipSuccess) goto oom;
+  if (dev_alloc(ctx, &p, nreal * sizeof(float), "hisq_nn_init") != HISQ_OK) goto oom;
   s->theta = static_cast<float2 *>(p);
-  if (hipMalloc(&p, nreal * sizeof(float)) != hipSuccess) goto oom;
+  if (dev_alloc(ctx, &p, nreal * sizeof(float), "hisq_nn_init") != HISQ_OK) goto oom;
   s->adam_m = static_cast<float *>(p);
-  if (hipMalloc(&p, nreal * sizeof(float)) != hipSuccess) goto oom;
+  if (dev_alloc(ctx, &p, nreal * sizeof(float), "hisq_nn_init") != HISQ_OK) goto oom;
   s->adam_v = static_cast<float *>(p);
-  if (hipMalloc(&p, nreal * sizeof(double)) != hipSuccess) goto oom;
+  if (dev_alloc(ctx, &p, nreal * sizeof(double), "hisq_nn_init") != HISQ_OK) goto oom;
   s->grad = static_cast<double *>(p);
   {
     std::vector<float> w(nreal);
@@ -1315,9 +1315,8 @@ extern "C" int hisq_nn_init(hisq_ctx *ctx, int layers, int channels, unsigned lo
   }
   return HISQ_OK;
 oom:
-  (void)hipGetLastError();
   nn_free_state(ctx);
-  return set_err(ctx, HISQ_ERR_OOM, "hisq_nn_init: allocation failed");
+  return HISQ_ERR_OOM;
 }
 
 extern "C" int hisq_nn_num_params(hisq_ctx *ctx) {

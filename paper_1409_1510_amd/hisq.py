@@ -63,7 +63,8 @@ class hisq_launch(ctypes.Structure):
 class hisq_cg_params(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("reliable_every", ctypes.c_int), ("link_prec", ctypes.c_int),
-                ("use_x0", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("use_x0", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("no_compaction", ctypes.c_int)]
 
 
 class hisq_cg_stats(ctypes.Structure):
@@ -73,7 +74,8 @@ class hisq_cg_stats(ctypes.Structure):
                 ("fell_back", ctypes.POINTER(ctypes.c_int)),
                 ("total_iters", ctypes.c_int), ("reliable_updates", ctypes.c_int),
                 ("dslash_site_rhs", ctypes.c_longlong), ("seconds", ctypes.c_double),
-                ("peak_bytes", ctypes.c_size_t), ("link_switch_iter", ctypes.c_int)]
+                ("peak_bytes", ctypes.c_size_t), ("link_switch_iter", ctypes.c_int),
+                ("compactions", ctypes.c_int)]
 
 
 def header_functions() -> list[str]:
@@ -375,21 +377,22 @@ class Lattice:
         return est.value, err.value, list(samples)
 
     def cg(self, mass, b, kind=HISQ_CG_F64, tol=1e-10, max_iter=20000, reliable_every=50,
-           link_prec=HISQ_F32, x0=None, check_every=0):
+           link_prec=HISQ_F32, x0=None, check_every=0, compaction=True):
         self._vec(b, HISQ_F64, "b")
         n = b.shape[0]
         x = self.empty(n, HISQ_F64) if x0 is None else self._vec(x0.clone(), HISQ_F64, "x0", n)
         p = hisq_cg_params(kind, tol, max_iter, reliable_every, link_prec, 0 if x0 is None else 1,
-                           check_every)
+                           check_every, 0 if compaction else 1)
         iters = (ctypes.c_int * n)()
         res = (ctypes.c_double * n)()
         conv = (ctypes.c_int * n)()
         fb = (ctypes.c_int * n)()
-        st = hisq_cg_stats(iters, res, conv, fb, 0, 0, 0, 0.0, 0, -1)
+        st = hisq_cg_stats(iters, res, conv, fb, 0, 0, 0, 0.0, 0, -1, 0)
         hisq_set_stream(self.ctx)
         rc = hisq_cg_mrhs(self.ctx, mass, n, b, x, p, st)
         info = dict(rc=rc, iters=list(iters), true_resid=list(res), converged=list(conv),
                     fell_back=list(fb), total_iters=st.total_iters,
                     reliable_updates=st.reliable_updates, dslash_site_rhs=st.dslash_site_rhs,
-                    seconds=st.seconds, peak_bytes=st.peak_bytes, link_switch_iter=st.link_switch_iter)
+                    seconds=st.seconds, peak_bytes=st.peak_bytes, link_switch_iter=st.link_switch_iter,
+                    compactions=st.compactions)
         return x, info

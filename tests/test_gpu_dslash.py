@@ -475,3 +475,21 @@ def test_multi_rhs_gain_over_single_rhs():
         r14 = _launch_ms(lat, hisq.HISQ_F32, n)
         print(f"r14 at n = {n}: {r14:.4f} ms against {ms[n]:.4f} ms ({100 * (ms[n] / r14 - 1):.1f} % faster)")
     lat.close()
+
+
+def test_register_tile_offsets_fit_32_bits_on_large_lattices():
+    """The register-tile Dslash indexes a rhs tile with 32-bit element offsets: on a lattice with
+    V/2 = 100.7M sites (256^3 x 12; only the context is created, nothing is allocated) a tile of
+    16 FP32 rhs (3 x 16 x V/2 > 2^32 elements) is refused, 8 are accepted, and the untuned
+    heuristic never proposes a tile that does not fit."""
+    lat = hisq.Lattice((256, 256, 256, 12), 0)
+    with pytest.raises(hisq.HisqError) as e:
+        hisq.hisq_set_launch(lat.ctx, hisq.HISQ_F32, 16, (16, 256, 0, 0, 0))
+    assert e.value.code == hisq.HISQ_ERR_ARG
+    hisq.hisq_set_launch(lat.ctx, hisq.HISQ_F32, 16, (8, 256, 0, 0, 0))
+    assert hisq.hisq_get_launch(lat.ctx, hisq.HISQ_F32, 16, 0)[0] == 8
+    for prec in (hisq.HISQ_F64, hisq.HISQ_F32):
+        for n in (8, 32, 64):
+            rt = hisq.hisq_get_launch(lat.ctx, prec, n, 1)[0]
+            assert 3 * rt * lat.vh < 2 ** 32
+    lat.close()

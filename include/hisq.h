@@ -116,6 +116,17 @@ int hisq_apply_m(hisq_ctx *ctx, int prec, double mass, int n, const void *in, vo
  * (re, im).  Asynchronous. */
 int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, const void *b, double *dots);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hisq_dot_mrhs with the same arguments, kernels and
+ * bit-identical results, which allocates nothing.  Its per-block partials go to a static device
+ * buffer of the library (8 MiB, 2^20 doubles, one per GPU, held until the process ends) instead
+ * of the context workspace.  It needs 2 * n * ceil(3 * (V/2) / 1024) <= 2^20 doubles (e.g. every
+ * n <= 64 up to 48^3 x 24 sites, n <= 85 at 64^3 x 16) and returns HISQ_ERR_ARG beyond that.
+ * Every call on a GPU shares that GPU's buffer: calls that overlap in time on one GPU (other
+ * streams or contexts) race and must be serialised by the caller; each call writes all the
+ * partials it reads, so nothing carries over between calls.  Asynchronous. */
+int hisq_dot_mrhs_noalloc(hisq_ctx *ctx, int prec, int n, const void *a, const void *b, double *dots);
+
 /* Launch configuration of the multi-rhs half Dslash.  Section 2 blocks the rhs in registers,
  * blocks sites x rhs in 2-d thread blocks, combines both, and picks the best launch
  * configuration for the GPU, the lattice size and n by automatic tuning.  The library does the

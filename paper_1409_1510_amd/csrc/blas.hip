@@ -12,6 +12,8 @@
 #include "internal.hpp"
 #include "cg_state.hpp"
 
+#include <mutex>
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -506,6 +508,65 @@ extern "C" int hisq_dot_mrhs(hisq_ctx *ctx, int prec, int n, const void *a, cons
   void *pp;
   RETCHK(ws_get(ctx, WS_PARTIAL, size_t(2 * n) * nblk * sizeof(double), &pp));
   double *partial = static_cast<double *>(pp);
+  int nb;
+  RETCHK(launch_dot_partials(ctx, prec, n, a, b, partial, &nb));
+  return launch_reduce_partials(ctx, partial, n, nb, 2, dots);
+}
+
+// ---- allocation-free per-rhs inner products ----
+//
+// hisq_dot_mrhs_noalloc keeps its per-block partials in this file-scope device array instead of
+// the context workspace: one copy per GPU, loaded with the library and held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (in host code the name stands for a
+// host-side shadow, not a device address); scratch_lookup() asks the runtime for the array's
+// device address once per device, with that device current, and every launch uses that address.
+constexpr size_t kScratchDoubles = size_t(1) << 20;  // 8 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int scratch_lookup(hisq_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return set_err(ctx, HISQ_ERR_ARG, "device index %d above the library's limit of %d", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[ctx->device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_err(ctx, HISQ_ERR_HIP, "hipGetSymbolAddress of the static scratch buffer failed: %s",
+                     hipGetErrorString(e));
+    }
+    g_scratch_dev[ctx->device] = p;
+  }
+  ctx->scratch_dev = g_scratch_dev[ctx->device];
+  return HISQ_OK;
+}
+
+extern "C" int hisq_dot_mrhs_noalloc(hisq_ctx *ctx, int prec, int n, const void *a, const void *b,
+                                     double *dots) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!a || !b || !dots) return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs_noalloc: null pointer");
+  if (!prec_valid(prec)) return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs_noalloc: bad precision %d", prec);
+  if (!elem_aligned(a, cplx_bytes(prec)) || !elem_aligned(b, cplx_bytes(prec)) || !elem_aligned(dots, sizeof(double)))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs_noalloc: vectors must be aligned to %zu bytes, dots to 8",
+                   cplx_bytes(prec));
+  if (n < 1 || n > HISQ_MAX_RHS)
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_dot_mrhs_noalloc: n = %d outside 1..%d", n, HISQ_MAX_RHS);
+  const int nblk = blas_nblk(ctx);
+  const size_t need = size_t(2 * n) * nblk;
+  if (need > kScratchDoubles)
+    return set_err(ctx, HISQ_ERR_ARG,
+                   "hisq_dot_mrhs_noalloc: %d rhs on %d sites per parity need %zu doubles of scratch, "
+                   "above the static buffer's %zu (at most %zu rhs on this lattice)",
+                   n, ctx->g.vh, need, kScratchDoubles, kScratchDoubles / (2 * size_t(nblk)));
+  if (!ctx->scratch_dev)
+    return set_err(ctx, HISQ_ERR_STATE, "hisq_dot_mrhs_noalloc: static scratch buffer not set up");
+  double *partial = static_cast<double *>(ctx->scratch_dev);
   int nb;
   RETCHK(launch_dot_partials(ctx, prec, n, a, b, partial, &nb));
   return launch_reduce_partials(ctx, partial, n, nb, 2, dots);

@@ -130,6 +130,11 @@ int hisq_create(hisq_ctx **out, const int dims[4], int device, void *stream) {
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
       lds > 0)
     ctx->lds_max = size_t(lds);
+  if (scratch_lookup(ctx) != HISQ_OK) {
+    set_err(nullptr, HISQ_ERR_HIP, "hisq_create: %s", ctx->err.c_str());
+    delete ctx;
+    return HISQ_ERR_HIP;
+  }
   *out = ctx;
   return HISQ_OK;
 }

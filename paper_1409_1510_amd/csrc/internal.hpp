@@ -81,6 +81,7 @@ struct hisq_ctx {
   void *pinned = nullptr;            // pinned host mirror of per-rhs residuals
   size_t pinned_bytes = 0;
   NNState *nn = nullptr;
+  void *scratch_dev = nullptr;       // device address of the library's static scratch array
   size_t dev_bytes = 0;              // device memory the context holds now (dev_alloc / dev_free)
   size_t dev_peak = 0;               // largest dev_bytes since the last reset (a solve resets it)
 };
@@ -111,6 +112,10 @@ int set_err(hisq_ctx *ctx, int code, const char *fmt, ...);
 // running peak dev_peak (links, workspace slots, tuning scratch, network state).
 int dev_alloc(hisq_ctx *ctx, void **p, size_t bytes, const char *what);
 void dev_free(hisq_ctx *ctx, void *p, size_t bytes);
+
+// Look up (once per device, device current) the static scratch array of the allocation-free
+// entry point and store its device address in ctx->scratch_dev.
+int scratch_lookup(hisq_ctx *ctx);
 
 // Grow-only device workspace slot.
 int ws_get(hisq_ctx *ctx, int slot, size_t bytes, void **out);

@@ -113,6 +113,7 @@ def _load():
         "hisq_dslash_mrhs": (cint, [vp, cint, cint, cint, vp, vp]),
         "hisq_apply_m": (cint, [vp, cint, cd, cint, vp, vp, vp]),
         "hisq_dot_mrhs": (cint, [vp, cint, cint, vp, vp, vp]),
+        "hisq_dot_mrhs_noalloc": (cint, [vp, cint, cint, vp, vp, vp]),
         "hisq_set_launch": (cint, [vp, cint, cint, ctypes.POINTER(hisq_launch)]),
         "hisq_get_launch": (cint, [vp, cint, cint, cint, ctypes.POINTER(hisq_launch)]),
         "hisq_autotune": (cint, [vp, cint, cint, cint, ctypes.POINTER(hisq_launch), dp]),
@@ -227,6 +228,10 @@ def hisq_apply_m(ctx, prec: int, mass: float, n: int, inp, out, pq_out=None) -> 
 
 def hisq_dot_mrhs(ctx, prec: int, n: int, a, b, dots) -> None:
     _check(ctx, _lib.hisq_dot_mrhs(ctx, int(prec), int(n), _ptr(a), _ptr(b), _ptr(dots)))
+
+
+def hisq_dot_mrhs_noalloc(ctx, prec: int, n: int, a, b, dots) -> None:
+    _check(ctx, _lib.hisq_dot_mrhs_noalloc(ctx, int(prec), int(n), _ptr(a), _ptr(b), _ptr(dots)))
 
 
 def hisq_set_launch(ctx, prec: int, n: int, cfg=None) -> None:

@@ -38,6 +38,7 @@ def test_null_context_is_rejected():
     assert lib.hisq_dslash_mrhs(None, 1, 0, 1, None, None) == hisq.HISQ_ERR_ARG
     assert lib.hisq_apply_m(None, 0, 0.1, 1, None, None, None) == hisq.HISQ_ERR_ARG
     assert lib.hisq_dot_mrhs(None, 0, 1, None, None, None) == hisq.HISQ_ERR_ARG
+    assert lib.hisq_dot_mrhs_noalloc(None, 0, 1, None, None, None) == hisq.HISQ_ERR_ARG
     assert lib.hisq_load_links(None, None, None, 7, 18) == hisq.HISQ_ERR_ARG
     assert lib.hisq_cg_mrhs(None, 0.1, 1, None, None, None, None) == hisq.HISQ_ERR_ARG
     assert lib.hisq_set_launch(None, 0, 1, None) == hisq.HISQ_ERR_ARG

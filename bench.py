@@ -12,7 +12,8 @@ Also reported on the same JSON line:
   roofline       : compulsory HBM bytes per half-Dslash launch / mean launch duration (HIP events
                    at the ends of the timed region on the launch stream, over its launches),
                    against 8 TB/s; the GPU clocks rocm-smi reports under the same load;
-  dslash_sweep   : n = 1, 2, 4, 8, 16 in FP64, FP32, FP32 with 14-real Naik, FP16 links;
+  dslash_sweep   : n = 1, 2, 4, 8, 16 in FP64, FP32 (Naik in 18, 14, 13, 9 reals), FP16 links
+                   (Naik in 18, 14, 9 reals);
   volume_sweep   : the FP32 half Dslash against the lattice volume;
   cg             : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
                    the mixed-precision solver (FP16 and FP32 links) and the plain FP64 solver;
@@ -83,6 +84,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def shipped_launch(hisq, dims, prec, recon, n, fused):
+    """The launch configuration the shipped tuning table holds for a case, or None."""
+    if not os.path.exists(hisq.TUNING_PATH):
+        return None
+    key = [*dims, prec, recon, n, fused]
+    for line in open(hisq.TUNING_PATH):
+        f = line.split()
+        if f and not f[0].startswith("#") and [int(v) for v in f[:8]] == key:
+            return tuple(int(v) for v in f[8:13])
+    return None
+
+
 def measured_traffic(config_tuple):
     """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE and
     WRITE_SIZE, each scaled by the same counter's reading for a copy kernel of known size), if the
@@ -131,7 +144,9 @@ SWEEP_N = (1, 2, 4, 8, 16)
 def sweep_cases(hisq):
     """(precision, Naik format, label) of the n/precision sweep."""
     return ((hisq.HISQ_F64, 18, "f64"), (hisq.HISQ_F32, 18, "f32"), (hisq.HISQ_F32, 14, "f32_r14"),
-            (hisq.HISQ_F16, 18, "f16links"), (hisq.HISQ_F16, 14, "f16links_r14"))
+            (hisq.HISQ_F32, 13, "f32_r13"), (hisq.HISQ_F32, 9, "f32_r9"),
+            (hisq.HISQ_F16, 18, "f16links"), (hisq.HISQ_F16, 14, "f16links_r14"),
+            (hisq.HISQ_F16, 9, "f16links_r9"))
 
 
 def _events(torch):
@@ -537,6 +552,10 @@ def main():
                          "timing does not depend on)")
     ap.add_argument("--profile-prec", default="f32", choices=["f32", "f16links"],
                     help="--profile: FP32 links or FP16 link storage (FP32 vectors either way)")
+    ap.add_argument("--profile-launch", default="",
+                    help="--profile: launch configuration rt,spb,nt,lds,xm to time (default: the "
+                         "shipped table's entry for the case, else the autotuner's choice), so that "
+                         "separate counter runs profile the same launch")
     ap.add_argument("--profile-sweep", action="store_true",
                     help="short run for rocprofv3: the counter-calibration kernel, then for every "
                          "case of the n/precision sweep 50 ms of untimed steps, 1 warm-up step and "
@@ -624,8 +643,8 @@ def main():
         srcs = {nn: (torch.from_numpy(synth.sources(dims, nn, 9)).to("cuda:0"),
                      torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0")) for nn in SWEEP_N}
         for prec, recon, name in sweep_cases(hisq):
-            if recon == 14:
-                lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 14)
+            if recon != 18:
+                lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, recon)
             for nn in SWEEP_N:
                 dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
                 a, b = srcs[nn][0].to(dt), srcs[nn][1].to(dt)
@@ -635,7 +654,7 @@ def main():
                 # the trace holds 2 k untimed launches, then 2 warmup and 6 timed launches per case
                 print(f"profile-sweep case {name} n {nn} launch {hisq.hisq_get_launch(lat.ctx, prec, nn, 0)} "
                       f"ramp {k}", flush=True)
-            if recon == 14:
+            if recon != 18:
                 lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
         lat.close()
         return
@@ -656,9 +675,16 @@ def main():
             v_e = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
             v_o = torch.randn(n, 3, lat.vh, dtype=torch.complex64, device="cuda:0")
             w_e, w_o = torch.empty_like(v_e), torch.empty_like(v_o)
+        # the launch a solve on this lattice would use: the shipped table's, else the tuner's
+        if args.profile_launch:
+            tuned = tuple(int(v) for v in args.profile_launch.split(","))
+        else:
+            tuned = shipped_launch(hisq, pdims, prec, 18, n, 0)
+            if tuned is None:
+                hisq.hisq_autotune(lat.ctx, prec, n, 0)
+                tuned = hisq.hisq_get_launch(lat.ctx, prec, n, 0)
         # the sustained load runs the same kernel with another rhs_per_thread (another kernel
         # symbol), so that the trace's statistics of the timed kernel hold the timed launches only
-        tuned = hisq.hisq_get_launch(lat.ctx, prec, n, 0)
         hisq.hisq_set_launch(lat.ctx, prec, n, (1 if tuned[0] > 1 else 2,) + tuned[1:])
         sustain(torch, dslash_step(lat, prec, v_e, v_o, w_e, w_o), RAMP_MS)
         hisq.hisq_set_launch(lat.ctx, prec, n, tuned)
@@ -725,8 +751,8 @@ def main():
                      torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0")) for nn in SWEEP_N}
         sweep = []
         for prec, recon, name in sweep_cases(hisq):
-            if recon == 14:
-                lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, 14)
+            if recon != 18:
+                lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, recon)
             for nn in SWEEP_N:
                 dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
                 a, b = srcs[nn][0].to(dt), srcs[nn][1].to(dt)
@@ -740,7 +766,7 @@ def main():
                               "gflops": round(pm.half_dslash_flops(vh, nn) / (ml * 1e-3) / 1e9, 1),
                               "compulsory_GBps": round(byt / (ml * 1e-3) / 1e9, 1),
                               "paper_model_GBps": round(paper_b / (ml * 1e-3) / 1e9, 1)})
-            if recon == 14:
+            if recon != 18:
                 lat.load_links(fat, naik, hisq.HISQ_LINKS_ALL, 18)
         result["dslash_sweep"] = sweep
         del srcs

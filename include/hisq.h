@@ -86,11 +86,20 @@ int hisq_set_stream(hisq_ctx *ctx, void *hip_stream);
  *   fat, naik : [V][4][3][3] complex128, host or device memory (detected), read only.
  *   copies    : HISQ_LINKS_* mask of device copies to build (FP64 is needed by HISQ_F64 calls
  *               and by the FP64 parts of every solver).
- *   naik_recon: 18 (store all 18 reals) or 14 (store rows 0 and 1 of N plus one complex scale
- *               z, row 2 = z * conj(row0 x row1); Section 1 and Section 2 name the 14-float
- *               Naik reconstruction).  r14 applies to the FP32 and FP16 copies; it is exact for
- *               N = c * U with U in U(3), and the call fails with HISQ_ERR_ARG if the given Naik
- *               links are not of that form (relative reconstruction error above 1e-10).
+ *   naik_recon: reals stored per Naik link in the FP32 and FP16 copies (Sections 1 and 2 name
+ *               the 14- and 9/13-float Naik reconstructions; the FP64 copy always keeps 18):
+ *               18: all 18 reals;
+ *               14: rows 0 and 1 of N plus one complex z, row 2 = z * conj(row0 x row1); exact
+ *                   for N = c * U with U in U(3);
+ *               13: rows 0 and 1 plus one real z (the same with z real); exact for N = c * U
+ *                   with c real and U in SU(3) (z = 1 / c);
+ *                9: N = c * U with c real and U in SU(3): u01, u02, u10, arg u00, arg u20 and c;
+ *                   |u00|, |u20| come from the unit norms of row 0 and column 0 and the four
+ *                   other entries from unitarity and det U = 1.
+ *               The call fails with HISQ_ERR_ARG if the given Naik links are not of the form the
+ *               format needs (relative reconstruction error above 1e-10).  The 13- and 9-real
+ *               formats run in the register-tile and 64-site LDS forms of the Dslash (not the
+ *               32-site or direction-pipelined forms, lds_links 4-6).
  * Non-finite link entries give HISQ_ERR_NONFINITE.  Replaces earlier links. */
 int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *naik, int copies, int naik_recon);
 
@@ -153,7 +162,9 @@ typedef struct {
   int xcd_map;           /* LDS form only: 0 = each XCD takes a contiguous range of sites; 1 =    */
                          /*    each XCD takes Lz/8 z slices for all t (needs (Lx/2)*Ly % 64 == 0 */
                          /*    and Lz % 8 == 0); 2 = each XCD takes 1/8 of the 64-site blocks of */
-                         /*    every (z, t) plane, z-major (needs (Lx/2)*Ly % 512 == 0)          */
+                         /*    every (z, t) plane, z-major (needs (Lx/2)*Ly % 512 == 0); 3 = the */
+                         /*    same blocks walked in z tiles of 4 slices, t within a tile (also  */
+                         /*    needs Lz % 4 == 0)                                                */
 } hisq_launch;
 
 /* Force the configuration for (prec, n), both forms (the fused-M form clamps rhs_per_thread to
@@ -219,7 +230,7 @@ typedef struct {
  *                   residual exceeds the iterated one by more than 2x in norm while the relative
  *                   residual is still above 1e-5, a stalled true residual, or a falling
  *                   convergence rate (the mean log true residual of the live rhs falls, over the
- *                   last 8 replacements, at less than 0.8 times the best such rate of the solve,
+ *                   last 8 replacements, at less than 0.9 times the best such rate of the solve,
  *                   while it is still 100x above tol).
  *   HISQ_FCG_NN   : flexible CG preconditioned by the network of hisq_nn_init/hisq_nn_train
  *                   (Notay's FCG with truncation 1, complex step sizes; FP32 body with

@@ -13,7 +13,8 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhisq.so")
 
 SOURCES = ["context.cpp", "links.hip", "dslash.hip", "dslash_f64.hip", "dslash_f32.hip",
-           "dslash_f16.hip", "blas.hip", "cg.cpp", "nn.hip", "trace.hip"]
+           "dslash_f32c.hip", "dslash_f16.hip", "dslash_f16c.hip", "blas.hip", "cg.cpp", "nn.hip",
+           "trace.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -188,8 +188,8 @@ extern "C" int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *n
   if (!fat || !naik) return set_err(ctx, HISQ_ERR_ARG, "hisq_load_links: null link pointer");
   if (copies <= 0 || copies > HISQ_LINKS_ALL)
     return set_err(ctx, HISQ_ERR_ARG, "hisq_load_links: bad copies mask %d", copies);
-  if (naik_recon != 18 && naik_recon != 14)
-    return set_err(ctx, HISQ_ERR_ARG, "hisq_load_links: naik_recon must be 18 or 14, got %d",
+  if (!naik_recon_valid(naik_recon))
+    return set_err(ctx, HISQ_ERR_ARG, "hisq_load_links: naik_recon must be 18, 14, 13 or 9, got %d",
                    naik_recon);
   HIPCHK(ctx, hipSetDevice(ctx->device));
   const Geometry &g = ctx->g;
@@ -238,17 +238,18 @@ extern "C" int hisq_load_links(hisq_ctx *ctx, const double *fat, const double *n
     for (int par = 0; par < 2; ++par) {
       double err = 0.0;
       int rc = launch_pack_links(ctx, dfat, dnaik, prec, recon, par, l.par[par],
-                                 recon == 14 ? &err : nullptr);
+                                 recon != 18 ? &err : nullptr);
       if (rc != HISQ_OK) {
         free_links(ctx);
         return rc;
       }
-      if (recon == 14 && !(err <= 1e-10)) {
+      if (recon != 18 && !(err <= 1e-10)) {
         free_links(ctx);
         return set_err(ctx, HISQ_ERR_ARG,
-                       "hisq_load_links: Naik links are not a multiple of a U(3) matrix "
-                       "(14-real reconstruction error %.3g); use naik_recon = 18",
-                       err);
+                       "hisq_load_links: Naik links are not of the form the %d-real storage needs "
+                       "(14: a multiple of a U(3) matrix; 13 and 9: a real multiple of an SU(3) "
+                       "matrix; reconstruction error %.3g); use naik_recon = 18",
+                       recon, err);
       }
     }
   }

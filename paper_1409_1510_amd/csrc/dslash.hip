@@ -20,21 +20,23 @@ DslashFn lookup(int prec, int recon, bool epi, const hisq_launch &c) {
   if (prec == HISQ_F64)
     return dslash_fn_f64(epi, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
   if (prec == HISQ_F32)
-    return dslash_fn_f32(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
-  return dslash_fn_f16(epi, recon == 14, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
+    return dslash_fn_f32(epi, recon, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
+  return dslash_fn_f16(epi, recon, c.rhs_per_thread, c.sites_per_block, c.nontemporal_links, lds);
 }
 
 size_t lds_bytes(int prec, int recon, const hisq_launch &c) {
   if (!c.lds_links) return 0;
   const size_t elem = prec == HISQ_F64 ? 16 : (prec == HISQ_F32 ? 8 : 4);
-  const bool r14 = prec != HISQ_F64 && recon == 14;
-  if (c.sites_per_block == 32)  // 32-site form: half of the whole-site form's pieces
-    return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 32 * elem + (r14 ? size_t(24) * 32 * 8 : 0) +
+  if (prec == HISQ_F64) recon = 18;
+  const bool r14 = recon == 14;
+  if (c.sites_per_block == 32)  // 32-site form: half of the whole-site form's pieces (18 and 14)
+    return size_t(link_planes_total(recon)) * 32 * elem + (r14 ? size_t(24) * 32 * 8 : 0) +
            dslash::kNbrTable32Bytes;
-  if (c.lds_links >= 4)  // two buffers of one direction's planes (+ rebuilt Naik rows)
+  if (c.lds_links >= 4)  // two buffers of one direction's planes (+ rebuilt Naik rows; 18 and 14)
     return 2 * size_t(r14 ? 32 : 36) * 64 * elem + (r14 ? size_t(12) * 64 * 8 : 0);
-  const size_t row2 = r14 ? size_t(24) * 64 * 8 : 0;
-  return size_t(link_planes_total(prec == HISQ_F64 ? 18 : recon)) * 64 * elem + row2 + dslash::kNbrTableBytes;
+  // staged planes, rebuilt Naik entries (arithmetic type: 8 bytes), neighbour table
+  return size_t(dslash::lds_staged_planes(recon)) * 64 * elem + size_t(dslash::lds_rebuilt_entries(recon)) * 64 * 8 +
+         dslash::kNbrTableBytes;
 }
 
 bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size_t lds_max = 0) {
@@ -44,8 +46,8 @@ bool config_valid(int prec, bool epi, const hisq_launch &c, int recon = 18, size
   if (c.sites_per_block != 32 && c.sites_per_block != 64 && c.sites_per_block != 256) return false;
   if (c.nontemporal_links != 0 && c.nontemporal_links != 1) return false;
   if (c.lds_links < 0 || c.lds_links > 6) return false;
-  if (c.xcd_map < 0 || c.xcd_map > 2 || (c.xcd_map != 0 && !c.lds_links)) return false;
-  return lookup(prec, 18, epi, c) != nullptr && lookup(prec, 14, epi, c) != nullptr;
+  if (c.xcd_map < 0 || c.xcd_map > 3 || (c.xcd_map != 0 && !c.lds_links)) return false;
+  return lookup(prec, prec == HISQ_F64 ? 18 : recon, epi, c) != nullptr;
 }
 
 // rhs tiles a workgroup of the direction-pipelined forms can hold (their waves keep every tile's
@@ -90,18 +92,21 @@ struct Geo {
   int ntiles, ngroups, nsblk, grid, xmap, zmap_bps, zmap_zr;
 };
 
-// XCD maps: both need whole 64-site blocks per (z, t) plane; the z-slab map (1) needs Lz
-// divisible by 8, the y-slab map (2) a multiple of 8 blocks per plane
+// XCD maps: all need whole 64-site blocks per (z, t) plane; the z-slab map (1) needs Lz
+// divisible by 8, the y-slab maps (2, 3) a multiple of 8 blocks per plane, and the z-tiled walk
+// of map 3 Lz divisible by 4
 bool map_possible(const Geometry &g, int xm) {
   if (xm == 0) return true;
   if ((g.lxh * g.ly) % 64 != 0) return false;
   if (xm == 1) return g.lz % 8 == 0;
   if (xm == 2) return (g.lxh * g.ly / 64) % 8 == 0;
+  if (xm == 3) return (g.lxh * g.ly / 64) % 8 == 0 && g.lz % 4 == 0;
   return false;
 }
 const char *map_requirement(int xm) {
   return xm == 1 ? "the z-slab XCD map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0"
-                 : "the y-slab XCD map needs (Lx/2)*Ly % 512 == 0";
+       : xm == 2 ? "the y-slab XCD map needs (Lx/2)*Ly % 512 == 0"
+                 : "the z-tiled y-slab XCD map needs (Lx/2)*Ly % 512 == 0 and Lz % 4 == 0";
 }
 
 Geo geometry(const Geometry &g, int n, const hisq_launch &c) {
@@ -203,7 +208,7 @@ int tune(hisq_ctx *ctx, int prec, int n, bool epi, hisq_launch *best_out, double
     for (int spb : {256, 64, 32})
       for (int nt : {0, 1})
         for (int lds = 0; lds <= 6; ++lds)
-          for (int xm : {0, 1, 2}) {
+          for (int xm : {0, 1, 2, 3}) {
             hisq_launch c{rt, spb, nt, lds, xm};
             if (!config_valid(prec, epi, c, ctx->links[prec].recon, ctx->lds_max)) continue;
             if (!map_possible(g, xm) || !fits_n(c, n) || !fits_lattice(c, g, prec)) continue;
@@ -279,7 +284,7 @@ extern "C" int hisq_set_launch(hisq_ctx *ctx, int prec, int n, const hisq_launch
     // (tuned or heuristic) configuration
     if (epi && c.sites_per_block == 32 && c.lds_links) continue;
     const int recon = ctx->links[prec].base ? ctx->links[prec].recon : 18;
-    if (c.xcd_map >= 1 && c.xcd_map <= 2 && !map_possible(ctx->g, c.xcd_map))
+    if (c.xcd_map >= 1 && c.xcd_map <= 3 && !map_possible(ctx->g, c.xcd_map))
       return set_err(ctx, HISQ_ERR_ARG, "%s", map_requirement(c.xcd_map));
     if (!config_valid(prec, epi, c, recon, ctx->lds_max)) {
       if (epi) {  // the fused-M form caps the register tile: use the largest valid one

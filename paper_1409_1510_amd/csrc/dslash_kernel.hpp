@@ -102,6 +102,91 @@ __device__ inline void load_link(const LT *__restrict__ links, int plane, unsign
   }
 }
 
+// Row 2 of a 13-real Naik link from rows 0 and 1 and the real scale z: z * conj(row0 x row1).
+template <typename Real>
+__device__ inline void naik_row2_real(Lnk<Real> &L, Real z) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+    Real cr = (L.re[0][b1] * L.re[1][b2] - L.im[0][b1] * L.im[1][b2]) -
+              (L.re[0][b2] * L.re[1][b1] - L.im[0][b2] * L.im[1][b1]);
+    Real ci = (L.re[0][b1] * L.im[1][b2] + L.im[0][b1] * L.re[1][b2]) -
+              (L.re[0][b2] * L.im[1][b1] + L.im[0][b2] * L.re[1][b1]);
+    L.re[2][b] = z * cr;
+    L.im[2][b] = -(z * ci);
+  }
+}
+
+__device__ inline void sincos_r(float x, float &s, float &c) { sincosf(x, &s, &c); }
+__device__ inline void sincos_r(double x, double &s, double &c) { sincos(x, &s, &c); }
+
+// A 9-real Naik link N = c U with U in SU(3), from u01, u02, u10, the phases th0 = arg u00 and
+// th2 = arg u20, and c: |u00| and |u20| follow from the unit norms of row 0 and column 0, and the
+// four remaining entries from the orthogonality of rows 1 and 2 to row 0 and from
+// row2 = conj(row0 x row1), row1 = conj(row2 x row0) (det U = 1); with n = 1 - |u00|^2:
+//   u11 = -(conj(u20 u02) + conj(u00) u01 u10) / n    u12 = (conj(u01 u20) - conj(u00) u02 u10) / n
+//   u21 = (conj(u10 u02) - conj(u00) u01 u20) / n     u22 = -(conj(u01 u10) + conj(u00) u02 u20) / n
+template <typename Real>
+__device__ inline void naik_from9(Lnk<Real> &L, Real u01r, Real u01i, Real u02r, Real u02i, Real u10r,
+                                  Real u10i, Real th0, Real th2, Real c) {
+  const Real nn = (u01r * u01r + u01i * u01i) + (u02r * u02r + u02i * u02i);
+  const Real a2 = Real(1) - nn;
+  const Real a0 = sqrt(a2 > Real(0) ? a2 : Real(0));
+  const Real b2 = nn - (u10r * u10r + u10i * u10i);
+  const Real b0 = sqrt(b2 > Real(0) ? b2 : Real(0));
+  Real s0, c0, s2, c2;
+  sincos_r(th0, s0, c0);
+  sincos_r(th2, s2, c2);
+  const Real u00r = a0 * c0, u00i = a0 * s0;
+  const Real u20r = b0 * c2, u20i = b0 * s2;
+  const Real inv = Real(1) / nn;
+  const Real pr = u20r * u02r - u20i * u02i, pi = u20r * u02i + u20i * u02r;  // u20 u02
+  const Real qr = u01r * u10r - u01i * u10i, qi = u01r * u10i + u01i * u10r;  // u01 u10
+  const Real tr = u01r * u20r - u01i * u20i, ti = u01r * u20i + u01i * u20r;  // u01 u20
+  const Real vr = u02r * u10r - u02i * u10i, vi = u02r * u10i + u02i * u10r;  // u02 u10
+  const Real u11r = -(pr + (u00r * qr + u00i * qi)) * inv, u11i = -(-pi + (u00r * qi - u00i * qr)) * inv;
+  const Real u12r = (tr - (u00r * vr + u00i * vi)) * inv, u12i = (-ti - (u00r * vi - u00i * vr)) * inv;
+  const Real u21r = (vr - (u00r * tr + u00i * ti)) * inv, u21i = (-vi - (u00r * ti - u00i * tr)) * inv;
+  const Real u22r = -(qr + (u00r * pr + u00i * pi)) * inv, u22i = -(-qi + (u00r * pi - u00i * pr)) * inv;
+  L.re[0][0] = c * u00r; L.im[0][0] = c * u00i;
+  L.re[0][1] = c * u01r; L.im[0][1] = c * u01i;
+  L.re[0][2] = c * u02r; L.im[0][2] = c * u02i;
+  L.re[1][0] = c * u10r; L.im[1][0] = c * u10i;
+  L.re[1][1] = c * u11r; L.im[1][1] = c * u11i;
+  L.re[1][2] = c * u12r; L.im[1][2] = c * u12i;
+  L.re[2][0] = c * u20r; L.im[2][0] = c * u20i;
+  L.re[2][1] = c * u21r; L.im[2][1] = c * u21i;
+  L.re[2][2] = c * u22r; L.im[2][2] = c * u22i;
+}
+
+// Load Naik hop k (8..15) at site s of a link array with plane stride vh, rebuilding what the
+// storage format NR (18, 14, 13 or 9, see link_plane) leaves out.
+template <typename Real, typename LT, int NR, bool NT>
+__device__ inline void load_naik(const LT *__restrict__ links, int k, unsigned vh, unsigned s, Lnk<Real> &L) {
+  if constexpr (NR == 18 || NR == 14) {
+    load_link<Real, LT, NR == 14, NT>(links, link_plane(k, NR), vh, s, L);
+  } else if constexpr (NR == 13) {
+    const LT *p = links + size_t(link_plane(k, NR)) * vh + s;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) ld_link<NT>(p + (a * 3 + b) * vh, L.re[a][b], L.im[a][b]);
+    Real zr, zi;
+    ld_link<NT>(links + size_t(naik_scale_plane(k, NR)) * vh + s, zr, zi);
+    naik_row2_real(L, (k & 1) ? zi : zr);
+  } else {
+    static_assert(NR == 9, "Naik storage formats: 18, 14, 13, 9");
+    const LT *p = links + size_t(link_plane(k, NR)) * vh + s;
+    Real a1r, a1i, a2r, a2i, b0r, b0i, t0, t2, cr, ci;
+    ld_link<NT>(p, a1r, a1i);
+    ld_link<NT>(p + vh, a2r, a2i);
+    ld_link<NT>(p + 2 * vh, b0r, b0i);
+    ld_link<NT>(p + 3 * vh, t0, t2);
+    ld_link<NT>(links + size_t(naik_scale_plane(k, NR)) * vh + s, cr, ci);
+    naik_from9(L, a1r, a1i, a2r, a2i, b0r, b0i, t0, t2, (k & 1) ? ci : cr);
+  }
+}
+
 // acc += sign * L v for the RT right-hand sides of the tile (sign -1 for backward hops).
 template <typename Real, int RT, bool NEG>
 __device__ inline void apply_hop(const Lnk<Real> &L, const typename CT<Real>::T *__restrict__ in,
@@ -326,7 +411,7 @@ __device__ inline bool tile_rhs(const Args &a, int r0, int (&rr)[RT], bool (&rac
 
 
 // SPB: sites per 256-thread workgroup (256: one tile per workgroup; 64: 4 tiles, one per wave).
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
+template <typename Real, typename LT, int RT, int NR, bool EPI, int SPB, bool NT>
 __global__ void __launch_bounds__(256) k_dslash(Args a) {
   using C = typename CT<Real>::T;
   constexpr int TPB = 256 / SPB;  // tiles per workgroup
@@ -368,7 +453,7 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
     const int t = rest / g.lz;
     const int x = 2 * xh + ((y + z + t + a.out_parity) & 1);
     const unsigned rowbase = s - xh;
-    constexpr int recon = R14 ? 14 : 18;
+    constexpr int recon = NR;
 #pragma unroll 1
     for (int mu = 0; mu < 4; ++mu) {
       unsigned f1, b1, f3, b3;
@@ -395,9 +480,9 @@ __global__ void __launch_bounds__(256) k_dslash(Args a) {
       apply_hop<Real, RT, false>(Lk, in, vh, f1, act, acc_re, acc_im);
       load_link<Real, LT, false, NT>(links, link_plane(4 + mu, recon), vh, s, Lk);
       apply_hop<Real, RT, true>(Lk, in, vh, b1, act, acc_re, acc_im);
-      load_link<Real, LT, R14, NT>(links, link_plane(8 + mu, recon), vh, s, Lk);
+      load_naik<Real, LT, NR, NT>(links, 8 + mu, vh, s, Lk);
       apply_hop<Real, RT, false>(Lk, in, vh, f3, act, acc_re, acc_im);
-      load_link<Real, LT, R14, NT>(links, link_plane(12 + mu, recon), vh, s, Lk);
+      load_naik<Real, LT, NR, NT>(links, 12 + mu, vh, s, Lk);
       apply_hop<Real, RT, true>(Lk, in, vh, b3, act, acc_re, acc_im);
     }
   }
@@ -460,8 +545,15 @@ constexpr int kBufWord3 = 0x00020000;
 // 8 x 3 rebuilt row-2 entries in the arithmetic type, then the neighbour table (16 byte
 // offsets per site).
 constexpr size_t kNbrTableBytes = size_t(16) * 64 * sizeof(unsigned);
-template <typename Real, typename LT, bool R14> constexpr size_t lds_nbr_offset() {
-  return size_t(R14 ? 128 : 144) * 64 * sizeof(LT) + (R14 ? size_t(24) * 64 * sizeof(typename CT<Real>::T) : 0);
+// rebuilt Naik entries kept in LDS per site (arithmetic type): row 2 of the 8 Naik links for
+// formats 14 and 13, all 9 entries for format 9
+constexpr int lds_rebuilt_entries(int nr) { return (nr == 14 || nr == 13) ? 24 : (nr == 9 ? 72 : 0); }
+// stored planes copied into LDS per site: all of them, except for format 9, whose Naik links are
+// rebuilt straight from global memory (keeping their 36 stored planes in LDS as well would take
+// a workgroup past half of a CU's LDS, one workgroup per CU instead of two)
+constexpr int lds_staged_planes(int nr) { return nr == 9 ? 72 : link_planes_total(nr); }
+template <typename Real, typename LT, int NR> constexpr size_t lds_nbr_offset() {
+  return size_t(lds_staged_planes(NR)) * 64 * sizeof(LT) + size_t(lds_rebuilt_entries(NR)) * 64 * sizeof(typename CT<Real>::T);
 }
 
 // LDS of the 32-site form: the same pieces for 32 sites.
@@ -474,17 +566,29 @@ constexpr size_t kNbrTable32Bytes = size_t(16) * 32 * sizeof(unsigned);
 // the XCD map of the launch (false: none).
 __device__ inline bool lds_block_at(const Args &a, int bid, int nbid, int &sblk) {
   const Geometry &g = a.g;
-  if (a.xmap == 2) {
-    // XCD k owns the blocks [k, k+1) * bps/8 of every (z, t) plane (with Lx = 32: four y rows)
-    // and walks the planes z-major.  The sites in flight on an XCD then span a few z slices of a
-    // thin slab whose t extent is the whole lattice, so the t and z neighbours they gather (the
-    // Naik hops reach 3 slices away) are mostly still in that XCD's L2.
+  if (a.xmap == 2 || a.xmap == 3) {
+    // XCD k owns the blocks [k, k+1) * bps/8 of every (z, t) plane (with Lx = 32: four y rows).
+    // Map 2 walks the planes z-major (t fastest): the sites in flight on an XCD span a few z
+    // slices of a thin slab whose t extent is the whole lattice, so the t and z neighbours they
+    // gather (the Naik hops reach 3 slices away) are mostly still in that XCD's L2 while Lt is
+    // small.  Map 3 walks z tiles of 4 slices, t within a tile and z fastest: a z neighbour is at
+    // most 3 planes back in the walk inside a tile and a t neighbour 4 or 12, so on large
+    // lattices (64^3 x 16: 4 blocks per plane and XCD, 16 planes in flight) the window that has
+    // to stay in L2 no longer grows with Lt; hops that cross a tile boundary re-fetch.
     const int k = bid & 7, j = bid >> 3;
     const int bpx = a.zmap_bps >> 3;
-    const int zt = j / bpx;  // z * Lt + t
-    const int z = zt / g.lt, t = zt - z * g.lt;
+    const int w = j / bpx;  // position of the (z, t) plane in the XCD's walk
+    int z, t;
+    if (a.xmap == 2) {
+      z = w / g.lt;
+      t = w - z * g.lt;
+    } else {
+      const int tile = w / (4 * g.lt), rem = w - tile * 4 * g.lt;
+      t = rem >> 2;
+      z = tile * 4 + (rem & 3);
+    }
     if (z >= g.lz) return false;
-    sblk = (t * g.lz + z) * a.zmap_bps + k * bpx + (j - zt * bpx);
+    sblk = (t * g.lz + z) * a.zmap_bps + k * bpx + (j - w * bpx);
   } else if (a.xmap == 1) {
     // XCD k owns the z slices [k Lz/8, (k+1) Lz/8) for every t: the z and t neighbours of its
     // sites stay mostly in its own L2 (with contiguous chunks, Lt = 8 would give each XCD a single
@@ -506,16 +610,24 @@ __device__ inline bool lds_block_at(const Args &a, int bid, int nbid, int &sblk)
 __device__ inline bool lds_block(const Args &a, int &sblk) { return lds_block_at(a, blockIdx.x, gridDim.x, sblk); }
 
 // Naik link k (0..7: hops 8 + k) of lane `lane` from the staged LDS copy: rows 0 and 1 from the
-// stored planes and, for 14-real links, row 2 from the planes rebuilt once per site.
-// (SB: sites per LDS plane)
-template <typename Real, typename LT, bool R14, int SB = 64>
+// stored planes and, for 14- and 13-real links, row 2 from the entries rebuilt once per site;
+// 9-real links entirely from the rebuilt entries.  (SB: sites per LDS plane)
+template <typename Real, typename LT, int NR, int SB = 64>
 __device__ inline void load_naik_lds(const LT *__restrict__ sl, const typename CT<Real>::T *__restrict__ row2,
                                      int k, int lane, Lnk<Real> &L) {
-  const int recon = R14 ? 14 : 18;
-  if constexpr (!R14) {
-    load_link<Real, LT, false, false>(sl, link_plane(8 + k, recon), unsigned(SB), unsigned(lane), L);
+  if constexpr (NR == 18) {
+    load_link<Real, LT, false, false>(sl, link_plane(8 + k, NR), unsigned(SB), unsigned(lane), L);
+  } else if constexpr (NR == 9) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const typename CT<Real>::T v = row2[(k * 9 + a * 3 + b) * SB + lane];
+        L.re[a][b] = v.x;
+        L.im[a][b] = v.y;
+      }
   } else {
-    const LT *p = sl + link_plane(8 + k, recon) * SB + lane;
+    const LT *p = sl + link_plane(8 + k, NR) * SB + lane;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -621,12 +733,12 @@ template <bool NT> __device__ inline __half2 ld_raw(const __half2 *p) {
 // the same per-64-site grouping of the fused <p, Mp> partials.
 // (the second launch bound is the waves per SIMD: two workgroups share a CU -- with 16 waves at
 // most 64 VGPRs, with 8 at most 128 -- except with FP64 links, whose 147 KB take a CU's LDS alone)
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
+template <typename Real, typename LT, int RT, int NR, bool EPI, int WPB, bool NT>
 __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) k_dslash_lds(Args a) {
   static_assert(WPB == 4 || WPB == 8 || WPB == 16, "4, 8 or 16 waves per workgroup");
   using C = typename CT<Real>::T;
-  constexpr int recon = R14 ? 14 : 18;
-  constexpr int PL = R14 ? 128 : 144;  // stored planes per site
+  constexpr int recon = NR;
+  constexpr int PL = lds_staged_planes(NR);  // stored planes per site staged in LDS
   extern __shared__ __align__(16) unsigned char smem_raw[];
   LT *sl = reinterpret_cast<LT *>(smem_raw);
   const Geometry &g = a.g;
@@ -645,11 +757,9 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) 
   // wave issues a batch of CH plane loads before it writes any of them, so their latencies
   // overlap.  With NT the global loads carry the non-temporal hint, so the streamed links do
   // not push the neighbour vectors out of L2.
-  {
-    static_assert(PL % WPB == 0, "planes divide evenly among the waves");
+  if constexpr (PL % WPB == 0 && (PL / WPB) % (PL / WPB % 9 == 0 ? 9 : 8) == 0) {
     constexpr int PPW = PL / WPB;
     constexpr int CH = PPW % 9 == 0 ? 9 : 8;
-    static_assert(PPW % CH == 0, "whole batches");
 #pragma unroll 1
     for (int c0 = 0; c0 < PPW; c0 += CH) {
       LT v[CH];
@@ -658,11 +768,50 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) 
 #pragma unroll
       for (int i = 0; i < CH; ++i) sl[(wave + (c0 + i) * WPB) * 64 + lane] = v[i];
     }
+  } else {  // plane counts that do not split into whole batches (Naik formats 13 and 9)
+    constexpr int PPW = (PL + WPB - 1) / WPB;
+    constexpr int CH = 8;
+#pragma unroll 1
+    for (int c0 = 0; c0 < PPW; c0 += CH) {
+      LT v[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int pl = wave + (c0 + i) * WPB;
+        if (pl < PL) v[i] = ld_raw<NT>(links + size_t(pl) * vh + sc);
+      }
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int pl = wave + (c0 + i) * WPB;
+        if (pl < PL) sl[pl * 64 + lane] = v[i];
+      }
+    }
+  }
+  // 14-, 13- and 9-real Naik links: rebuild what the format leaves out once per site (not once
+  // per rhs tile) into LDS entries of the arithmetic type after the staged planes, with the same
+  // arithmetic as load_naik: the whole link for 9 here, from global memory; row 2 for 14 and 13
+  // from the staged planes after the barrier below
+  C *row2 = reinterpret_cast<C *>(sl + PL * 64);
+  if constexpr (NR == 9) {
+    for (int item = threadIdx.x; item < 8 * 64; item += 64 * WPB) {
+      const int k = item >> 6, ln = item & 63;
+      const unsigned site = sblk * 64 + ln;
+      Lnk<Real> Lk;
+      load_naik<Real, LT, NR, NT>(links, 8 + k, vh, site < vh ? site : 0u, Lk);
+#pragma unroll
+      for (int ra = 0; ra < 3; ++ra)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          C v;
+          v.x = Lk.re[ra][b];
+          v.y = Lk.im[ra][b];
+          row2[(k * 9 + ra * 3 + b) * 64 + ln] = v;
+        }
+    }
   }
   // neighbour table: the byte offsets (within a colour plane) of the 16 neighbours of the 64
   // sites, [mu][site][+1, -1, +3, -3], built once per workgroup (one hop per wave and lane with
   // 16 waves) so the rhs-tile loop does no site arithmetic
-  unsigned *nbt = reinterpret_cast<unsigned *>(smem_raw + lds_nbr_offset<Real, LT, R14>());
+  unsigned *nbt = reinterpret_cast<unsigned *>(smem_raw + lds_nbr_offset<Real, LT, NR>());
   {
     const unsigned q1 = fast_div(sc, a.div_xh);
     const unsigned q2 = fast_div(q1, a.div_y);
@@ -680,14 +829,11 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) 
     }
   }
   __syncthreads();
-  // 14-real Naik links: rebuild row 2 once per site (not once per rhs tile) into LDS planes of
-  // the arithmetic type after the stored planes, with the same arithmetic as load_link
-  C *row2 = reinterpret_cast<C *>(sl + PL * 64);
-  if constexpr (R14) {
+  if constexpr (NR == 14 || NR == 13) {
     for (int item = threadIdx.x; item < 8 * 64; item += 64 * WPB) {
       const int k = item >> 6, ln = item & 63;
       Lnk<Real> Lk;
-      load_link<Real, LT, true, false>(sl, link_plane(8 + k, recon), 64u, ln, Lk);
+      load_naik<Real, LT, NR, false>(sl, 8 + k, 64u, unsigned(ln), Lk);
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         C v;
@@ -698,7 +844,6 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) 
     }
     __syncthreads();
   }
-
   // a tile spans RT * 3 colour planes of less than 4 GiB in all (checked at launch)
   const unsigned plane_bytes = vh * unsigned(sizeof(C));
   for (int tile = wave; tile < a.ntiles; tile += WPB) {
@@ -733,9 +878,9 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 1 : 2)) 
       apply_hop_buf<Real, RT, false>(Lk, rs, plane_bytes, nb.x, rr, acc_re, acc_im);
       load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 64u, lane, Lk);
       apply_hop_buf<Real, RT, true>(Lk, rs, plane_bytes, nb.y, rr, acc_re, acc_im);
-      load_naik_lds<Real, LT, R14>(sl, row2, mu, lane, Lk);
+      load_naik_lds<Real, LT, NR>(sl, row2, mu, lane, Lk);
       apply_hop_buf<Real, RT, false>(Lk, rs, plane_bytes, nb.z, rr, acc_re, acc_im);
-      load_naik_lds<Real, LT, R14>(sl, row2, 4 + mu, lane, Lk);
+      load_naik_lds<Real, LT, NR>(sl, row2, 4 + mu, lane, Lk);
       apply_hop_buf<Real, RT, true>(Lk, rs, plane_bytes, nb.w, rr, acc_re, acc_im);
     }
     bool act[RT];
@@ -853,9 +998,9 @@ __global__ void __launch_bounds__(64 * WPB, WPB / 4 * (sizeof(LT) > 8 ? 2 : 4)) 
       apply_hop_buf32<Real, RT, false>(Lk, rs, plane_bytes, nb.x + hoff, acc_re, acc_im);
       load_link<Real, LT, false, false>(sl, link_plane(4 + mu, recon), 32u, unsigned(si), Lk);
       apply_hop_buf32<Real, RT, true>(Lk, rs, plane_bytes, nb.y + hoff, acc_re, acc_im);
-      load_naik_lds<Real, LT, R14, 32>(sl, row2, mu, si, Lk);
+      load_naik_lds<Real, LT, R14 ? 14 : 18, 32>(sl, row2, mu, si, Lk);
       apply_hop_buf32<Real, RT, false>(Lk, rs, plane_bytes, nb.z + hoff, acc_re, acc_im);
-      load_naik_lds<Real, LT, R14, 32>(sl, row2, 4 + mu, si, Lk);
+      load_naik_lds<Real, LT, R14 ? 14 : 18, 32>(sl, row2, 4 + mu, si, Lk);
       apply_hop_buf32<Real, RT, true>(Lk, rs, plane_bytes, nb.w + hoff, acc_re, acc_im);
     }
     C *__restrict__ out = static_cast<C *>(a.out) + size_t(r0) * 3 * vh;
@@ -1054,15 +1199,15 @@ __global__ void __launch_bounds__(64 * WPB, (WPB == 16 && TPW == 1) ? 8 : 1) k_d
 
 using DslashFn = void (*)(const Args &, dim3, hipStream_t);
 
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int SPB, bool NT>
+template <typename Real, typename LT, int RT, int NR, bool EPI, int SPB, bool NT>
 void launch_t(const Args &a, dim3 grid, hipStream_t st) {
-  k_dslash<Real, LT, RT, R14, EPI, SPB, NT><<<grid, 256, 0, st>>>(a);
+  k_dslash<Real, LT, RT, NR, EPI, SPB, NT><<<grid, 256, 0, st>>>(a);
 }
 
-template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, bool NT>
+template <typename Real, typename LT, int RT, int NR, bool EPI, int WPB, bool NT>
 void launch_lds(const Args &a, dim3 grid, hipStream_t st) {
-  constexpr size_t lds = lds_nbr_offset<Real, LT, R14>() + kNbrTableBytes;
-  k_dslash_lds<Real, LT, RT, R14, EPI, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
+  constexpr size_t lds = lds_nbr_offset<Real, LT, NR>() + kNbrTableBytes;
+  k_dslash_lds<Real, LT, RT, NR, EPI, WPB, NT><<<grid, 64 * WPB, lds, st>>>(a);
 }
 
 template <typename Real, typename LT, int RT, bool R14, bool EPI, int WPB, int TPW, bool NT>
@@ -1087,13 +1232,13 @@ DslashFn pick_mu(int rt, int lds) {
   return nullptr;
 }
 
-template <typename Real, typename LT, bool R14, bool EPI, int WPB, bool NT>
+template <typename Real, typename LT, int NR, bool EPI, int WPB, bool NT>
 DslashFn pick_lds_rt(int rt) {
   switch (rt) {
-    case 1: return launch_lds<Real, LT, 1, R14, EPI, WPB, NT>;
-    case 2: return launch_lds<Real, LT, 2, R14, EPI, WPB, NT>;
+    case 1: return launch_lds<Real, LT, 1, NR, EPI, WPB, NT>;
+    case 2: return launch_lds<Real, LT, 2, NR, EPI, WPB, NT>;
     case 4:
-      if constexpr (WPB <= 8) return launch_lds<Real, LT, 4, R14, EPI, WPB, NT>;
+      if constexpr (WPB <= 8) return launch_lds<Real, LT, 4, NR, EPI, WPB, NT>;
       return nullptr;
     default: return nullptr;
   }
@@ -1113,56 +1258,65 @@ DslashFn pick_lds32(int rt, int lds) {
   return nullptr;
 }
 
-// lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves, 3 = 16 waves
-template <typename Real, typename LT, bool R14, bool EPI, bool NT>
+// lds: 1 = 4 waves per 64-site workgroup, 2 = 8 waves, 3 = 16 waves; 4-6 the direction-pipelined
+// forms (Naik formats 18 and 14 only)
+template <typename Real, typename LT, int NR, bool EPI, bool NT>
 DslashFn pick_lds(int rt, int lds) {
   if constexpr (sizeof(LT) > 8) {  // FP64: the whole-site forms only (one workgroup per CU)
-    if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
-    if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
-    if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);
+    if (lds == 1) return pick_lds_rt<Real, LT, NR, EPI, 4, NT>(rt);
+    if (lds == 2) return pick_lds_rt<Real, LT, NR, EPI, 8, NT>(rt);
+    if (lds == 3) return pick_lds_rt<Real, LT, NR, EPI, 16, NT>(rt);
     return nullptr;
   } else {
-    if (lds >= 4) return pick_mu<Real, LT, R14, EPI, NT>(rt, lds);
-    if (lds == 1) return pick_lds_rt<Real, LT, R14, EPI, 4, NT>(rt);
-    if (lds == 2) return pick_lds_rt<Real, LT, R14, EPI, 8, NT>(rt);
-    if (lds == 3) return pick_lds_rt<Real, LT, R14, EPI, 16, NT>(rt);
+    if (lds >= 4) {
+      if constexpr (NR == 18 || NR == 14) return pick_mu<Real, LT, NR == 14, EPI, NT>(rt, lds);
+      return nullptr;
+    }
+    if (lds == 1) return pick_lds_rt<Real, LT, NR, EPI, 4, NT>(rt);
+    if (lds == 2) return pick_lds_rt<Real, LT, NR, EPI, 8, NT>(rt);
+    if (lds == 3) return pick_lds_rt<Real, LT, NR, EPI, 16, NT>(rt);
     return nullptr;
   }
 }
 
-template <typename Real, typename LT, bool R14, bool EPI, int SPB, bool NT>
+template <typename Real, typename LT, int NR, bool EPI, int SPB, bool NT>
 DslashFn pick_rt(int rt) {
   switch (rt) {
-    case 1: return launch_t<Real, LT, 1, R14, EPI, SPB, NT>;
-    case 2: return launch_t<Real, LT, 2, R14, EPI, SPB, NT>;
-    case 4: return launch_t<Real, LT, 4, R14, EPI, SPB, NT>;
-    case 8: return launch_t<Real, LT, 8, R14, EPI, SPB, NT>;
+    case 1: return launch_t<Real, LT, 1, NR, EPI, SPB, NT>;
+    case 2: return launch_t<Real, LT, 2, NR, EPI, SPB, NT>;
+    case 4: return launch_t<Real, LT, 4, NR, EPI, SPB, NT>;
+    case 8: return launch_t<Real, LT, 8, NR, EPI, SPB, NT>;
     default:
-      if constexpr (!EPI && sizeof(Real) == 4) return launch_t<Real, LT, 16, R14, EPI, SPB, NT>;
+      if constexpr (!EPI && sizeof(Real) == 4) return launch_t<Real, LT, 16, NR, EPI, SPB, NT>;
       return nullptr;
   }
 }
 
-template <typename Real, typename LT, bool R14>
+// Every form for Naik storage format NR (the 32-site and direction-pipelined forms: 18 and 14).
+template <typename Real, typename LT, int NR>
 DslashFn pick_all(bool epi, int rt, int spb, bool nt, int lds) {
   if (lds) {
-    if (spb == 32) return epi ? nullptr : (nt ? pick_lds32<Real, LT, R14, true>(rt, lds) : pick_lds32<Real, LT, R14, false>(rt, lds));
+    if (spb == 32) {
+      if constexpr (NR == 18 || NR == 14)
+        return epi ? nullptr : (nt ? pick_lds32<Real, LT, NR == 14, true>(rt, lds) : pick_lds32<Real, LT, NR == 14, false>(rt, lds));
+      return nullptr;
+    }
     if (spb != 64) return nullptr;
-    if (nt) return epi ? pick_lds<Real, LT, R14, true, true>(rt, lds) : pick_lds<Real, LT, R14, false, true>(rt, lds);
-    return epi ? pick_lds<Real, LT, R14, true, false>(rt, lds) : pick_lds<Real, LT, R14, false, false>(rt, lds);
+    if (nt) return epi ? pick_lds<Real, LT, NR, true, true>(rt, lds) : pick_lds<Real, LT, NR, false, true>(rt, lds);
+    return epi ? pick_lds<Real, LT, NR, true, false>(rt, lds) : pick_lds<Real, LT, NR, false, false>(rt, lds);
   }
   if (spb != 64 && spb != 256) return nullptr;
   if (epi) {
-    if (spb == 64) return nt ? pick_rt<Real, LT, R14, true, 64, true>(rt) : pick_rt<Real, LT, R14, true, 64, false>(rt);
-    return nt ? pick_rt<Real, LT, R14, true, 256, true>(rt) : pick_rt<Real, LT, R14, true, 256, false>(rt);
+    if (spb == 64) return nt ? pick_rt<Real, LT, NR, true, 64, true>(rt) : pick_rt<Real, LT, NR, true, 64, false>(rt);
+    return nt ? pick_rt<Real, LT, NR, true, 256, true>(rt) : pick_rt<Real, LT, NR, true, 256, false>(rt);
   }
-  if (spb == 64) return nt ? pick_rt<Real, LT, R14, false, 64, true>(rt) : pick_rt<Real, LT, R14, false, 64, false>(rt);
-  return nt ? pick_rt<Real, LT, R14, false, 256, true>(rt) : pick_rt<Real, LT, R14, false, 256, false>(rt);
+  if (spb == 64) return nt ? pick_rt<Real, LT, NR, false, 64, true>(rt) : pick_rt<Real, LT, NR, false, 64, false>(rt);
+  return nt ? pick_rt<Real, LT, NR, false, 256, true>(rt) : pick_rt<Real, LT, NR, false, 256, false>(rt);
 }
 
 }  // namespace dslash
 
 // per-precision tables (dslash_f64.hip, dslash_f32.hip, dslash_f16.hip)
 dslash::DslashFn dslash_fn_f64(bool epi, int rt, int spb, bool nt, int lds);
-dslash::DslashFn dslash_fn_f32(bool epi, bool r14, int rt, int spb, bool nt, int lds);
-dslash::DslashFn dslash_fn_f16(bool epi, bool r14, int rt, int spb, bool nt, int lds);
+dslash::DslashFn dslash_fn_f32(bool epi, int recon, int rt, int spb, bool nt, int lds);
+dslash::DslashFn dslash_fn_f16(bool epi, int recon, int rt, int spb, bool nt, int lds);

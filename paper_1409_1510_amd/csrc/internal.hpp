@@ -27,12 +27,29 @@ struct Geometry {
 //            k = 4 + mu   fat backward  X(x - mu, mu)^dag      (stored already daggered)
 //            k = 8 + mu   Naik forward  N(x, mu)
 //            k = 12 + mu  Naik backward N(x - 3mu, mu)^dag     (stored already daggered)
-// Each hop is stored as planes of V/2 complex numbers (one plane per stored matrix entry): 9
-// planes for a full matrix, 7 for a reconstructed Naik link (rows 0 and 1, then the scale z).
-__host__ __device__ inline int link_plane(int k, int recon) {
-  return k < 8 ? 9 * k : 72 + (k - 8) * (recon == 14 ? 7 : 9);
+// Each hop is stored as planes of V/2 complex numbers (one plane per stored complex entry).  Fat
+// links: 9 planes.  Naik links by storage format (recon):
+//   18: the 9 entries;
+//   14: rows 0 and 1, then the complex scale z (row 2 = z conj(row0 x row1));
+//   13: rows 0 and 1; the real scale z of hops 8 + 2j and 9 + 2j shares one plane (re, im);
+//    9: N = c U, U in SU(3): u01, u02, u10 and the plane (arg u00, arg u20); the real c of hops
+//       8 + 2j and 9 + 2j shares one plane.
+__host__ __device__ constexpr int naik_planes(int recon) {
+  return recon == 18 ? 9 : (recon == 14 ? 7 : (recon == 13 ? 6 : 4));
 }
-__host__ __device__ inline int link_planes_total(int recon) { return recon == 14 ? 72 + 56 : 144; }
+__host__ __device__ constexpr int link_plane(int k, int recon) {
+  return k < 8 ? 9 * k : 72 + (k - 8) * naik_planes(recon);
+}
+// plane of the real scale of Naik hop k (formats 13 and 9; the re part for even k, im for odd)
+__host__ __device__ constexpr int naik_scale_plane(int k, int recon) {
+  return 72 + 8 * naik_planes(recon) + (k - 8) / 2;
+}
+__host__ __device__ constexpr int link_planes_total(int recon) {
+  return 72 + 8 * naik_planes(recon) + ((recon == 13 || recon == 9) ? 4 : 0);
+}
+__host__ __device__ constexpr bool naik_recon_valid(int recon) {
+  return recon == 18 || recon == 14 || recon == 13 || recon == 9;
+}
 
 struct LinkCopy {
   void *base = nullptr;              // one allocation holding both parities

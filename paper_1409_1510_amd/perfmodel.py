@@ -20,8 +20,11 @@ REAL_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
 def link_reals(recon: int = 18) -> int:
-    """Reals stored for the 16 links an output site reads."""
-    return 8 * 18 + 8 * (14 if recon == 14 else 18)
+    """Reals stored for the 16 links an output site reads: 8 fat links of 18 reals and 8 Naik
+    links of `recon` reals (18, 14, 13 or 9)."""
+    if recon not in (18, 14, 13, 9):
+        raise ValueError(f"Naik storage format {recon}: 18, 14, 13 or 9")
+    return 8 * 18 + 8 * recon
 
 
 def paper_model_bytes(n: int, recon: int = 18, real_bytes: int = 4) -> int:

@@ -20,7 +20,7 @@ if ROOT not in sys.path:
 import synth  # noqa: E402
 from paper_1409_1510_amd import hisq  # noqa: E402
 
-RHS = {"c1": (1, 2, 4, 8, 16), "c2": (8,), "c3": (8, 16), "c4": (8, 32)}
+RHS = {"c1": (1, 2, 4, 8, 16), "c2": (8,), "c3": (8, 16), "c4": (8, 16, 32)}
 
 
 def main():

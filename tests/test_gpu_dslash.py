@@ -38,7 +38,7 @@ def test_f64_matches_oracle(dims, n, out_parity):
 
 
 @pytest.mark.parametrize("dims,n", CASES)
-@pytest.mark.parametrize("recon", [18, 14])
+@pytest.mark.parametrize("recon", [18, 14, 13, 9])
 def test_f32_matches_oracle(dims, n, recon):
     lat, fat, naik = make_lattice(dims, 102, recon=recon)
     v = _vecs(dims, n, 103)
@@ -51,7 +51,7 @@ def test_f32_matches_oracle(dims, n, recon):
     lat.close()
 
 
-@pytest.mark.parametrize("recon", [18, 14])
+@pytest.mark.parametrize("recon", [18, 14, 13, 9])
 def test_f16_links_matches_oracle(recon):
     dims, n = (8, 6, 4, 10), 5
     lat, fat, naik = make_lattice(dims, 104, recon=recon)
@@ -67,7 +67,8 @@ def test_f16_links_matches_oracle(recon):
 
 @pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
                                         (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 18),
-                                        (hisq.HISQ_F16, 14)])
+                                        (hisq.HISQ_F16, 14), (hisq.HISQ_F32, 13),
+                                        (hisq.HISQ_F32, 9), (hisq.HISQ_F16, 9)])
 def test_multi_rhs_bit_identical_to_single(prec, recon):
     dims = (8, 6, 4, 10)
     lat, fat, naik = make_lattice(dims, 106, recon=recon)
@@ -177,9 +178,16 @@ def test_state_and_link_errors():
     with pytest.raises(hisq.HisqError) as e:
         lat.load_links(bad, naik)
     assert e.value.code == hisq.HISQ_ERR_NONFINITE
-    with pytest.raises(hisq.HisqError) as e:  # fat links are not c * U(3): r14 must refuse
-        lat.load_links(naik, fat, naik_recon=14)
-    assert e.value.code == hisq.HISQ_ERR_ARG
+    for recon in (14, 13, 9):  # fat links are not c * U(3): the compressed formats must refuse
+        with pytest.raises(hisq.HisqError) as e:
+            lat.load_links(naik, fat, naik_recon=recon)
+        assert e.value.code == hisq.HISQ_ERR_ARG
+    u1 = naik * np.exp(0.3j)  # c complex: U(3) but not a real multiple of SU(3)
+    lat.load_links(fat, u1, naik_recon=14)
+    for recon in (13, 9):
+        with pytest.raises(hisq.HisqError) as e:
+            lat.load_links(fat, u1, naik_recon=recon)
+        assert e.value.code == hisq.HISQ_ERR_ARG
     # only the FP32 copy: FP64 calls fail cleanly
     lat.load_links(fat, naik, copies=hisq.HISQ_LINKS_F32)
     with pytest.raises(hisq.HisqError) as e:
@@ -262,19 +270,23 @@ def test_full_size_32c8_sampled_sites():
 
 
 ALL_CFGS = ([(rt, spb, nt, 0, 0) for rt in (1, 2, 4, 8, 16) for spb in (256, 64) for nt in (0, 1)]
-            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3, 4, 5, 6) for xm in (0, 1, 2)
+            + [(rt, 64, nt, lds, xm) for rt in (1, 2, 4) for lds in (1, 2, 3, 4, 5, 6) for xm in (0, 1, 2, 3)
                for nt in (0, 1)]
-            + [(rt, 32, nt, lds, xm) for rt in (1, 2, 4) for lds in (0, 1, 2, 3) for xm in (0, 1, 2)
+            + [(rt, 32, nt, lds, xm) for rt in (1, 2, 4) for lds in (0, 1, 2, 3) for xm in (0, 1, 2, 3)
                for nt in (0, 1)])
 
 
-def _cfg_valid(prec, cfg, dims):
+def _cfg_valid(prec, cfg, dims, recon=18):
     """The launch rules of the header: FP64 has no 16-rhs tile and no direction-pipelined form;
     the 16-wave LDS form and the direction-pipelined forms take at most 2 rhs per thread; the
-    z-slab map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0, the y-slab map (Lx/2)*Ly % 512 == 0."""
+    z-slab map needs (Lx/2)*Ly % 64 == 0 and Lz % 8 == 0, the y-slab map (Lx/2)*Ly % 512 == 0
+    and its z-tiled walk also Lz % 4 == 0; 13- and 9-real Naik links have no 32-site and no
+    direction-pipelined form."""
     rt, spb, nt, lds, xm = cfg
     plane = dims[0] // 2 * dims[1]
     if prec == hisq.HISQ_F64 and (rt == 16 or lds >= 4):
+        return False
+    if recon in (13, 9) and lds and (spb == 32 or lds >= 4):
         return False
     if spb == 32 and not (lds in (1, 2) and rt <= 2):
         return False
@@ -282,21 +294,25 @@ def _cfg_valid(prec, cfg, dims):
         return False
     if xm == 1 and not (plane % 64 == 0 and dims[2] % 8 == 0):
         return False
-    if xm == 2 and plane % 512 != 0:
+    if xm in (2, 3) and plane % 512 != 0:
+        return False
+    if xm == 3 and dims[2] % 4 != 0:
         return False
     return True
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4), (16, 64, 4, 4), (6, 6, 4, 6)])
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 8, 8, 4), (16, 64, 8, 4), (6, 6, 4, 6)])
 @pytest.mark.parametrize("prec,recon", [(hisq.HISQ_F64, 18), (hisq.HISQ_F32, 18),
-                                        (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14)])
+                                        (hisq.HISQ_F32, 14), (hisq.HISQ_F16, 14),
+                                        (hisq.HISQ_F32, 9), (hisq.HISQ_F16, 13)])
 def test_every_launch_config_bit_identical(prec, recon, dims):
     """All register tiles, workgroup shapes, cache hints, the LDS-staged form and the XCD maps give
     the same bits, for the plain half Dslash and for the fused M operator (including its FP64
     <p, Mp> reduction; the 32-site form is plain-only and leaves the fused configuration as it
     was), and the autotuned choice is one of them.  Exactly the configurations the
-    header rules out are refused.  (16, 8, 8, 4) admits the z-slab XCD map, (16, 64, 4, 4) the
-    y-slab map; (6, 6, 4, 6) has V/2 = 432, so the last 64-site block of the LDS forms is ragged."""
+    header rules out are refused.  (16, 8, 8, 4) admits the z-slab XCD map, (16, 64, 8, 4) the
+    y-slab maps (two z tiles for the tiled walk); (6, 6, 4, 6) has V/2 = 432, so the last 64-site
+    block of the LDS forms is ragged."""
     n, mass = 11, 0.1
     lat, fat, naik = make_lattice(dims, 120, recon=recon)
     dt = torch.complex128 if prec == hisq.HISQ_F64 else torch.complex64
@@ -310,9 +326,9 @@ def test_every_launch_config_bit_identical(prec, recon, dims):
             hisq.hisq_set_launch(lat.ctx, prec, n, cfg)
         except hisq.HisqError as e:
             assert e.code == hisq.HISQ_ERR_ARG
-            assert not _cfg_valid(prec, cfg, dims), cfg
+            assert not _cfg_valid(prec, cfg, dims, recon), cfg
             continue
-        assert _cfg_valid(prec, cfg, dims), cfg
+        assert _cfg_valid(prec, cfg, dims, recon), cfg
         tried += 1
         out = lat.dslash(1, prec, v)
         m, pq = lat.apply_m(prec, mass, v, with_pq=True)

@@ -65,3 +65,32 @@ def test_gauge_rotated_tiled_links_lose_the_period():
     dv = oracle.dslash_full(fat, naik, v, dims)
     d_rot = oracle.dslash_full(rf, rn, np.einsum("sab,sb->sa", om, v), dims)
     assert np.max(np.abs(d_rot - np.einsum("sab,sb->sa", om, dv))) <= 1e-12 * np.max(np.abs(dv))
+
+
+def test_naik_links_have_the_13_and_9_real_forms():
+    """Readings of the 13- and 9-real Naik formats: the synthetic N = -U/24 is a real multiple
+    c = -1/24 of an SU(3) matrix (det N = c^3 is real), so row 2 = conj(row0 x row1) / c with a
+    real scale (13 reals); and U is fixed by u01, u02, u10 and the phases of u00 and u20 (9 reals
+    with c): |u00|^2 = 1 - |u01|^2 - |u02|^2 and |u20|^2 = |u01|^2 + |u02|^2 - |u10|^2 by the unit
+    norms of row 0 and column 0, the other four entries by the orthogonality of rows 1 and 2 to
+    row 0 together with row2 = conj(row0 x row1) and row1 = conj(row2 x row0)."""
+    fat, naik = synth.gauge_links((4, 4, 4, 4), 22)
+    n = naik.reshape(-1, 3, 3)
+    det = np.linalg.det(n)
+    assert np.max(np.abs(det.imag)) <= 1e-15 and np.allclose(np.cbrt(det.real), -1.0 / 24, atol=1e-14)
+    c = np.cbrt(det.real)
+    row2 = np.conj(np.cross(n[:, 0, :], n[:, 1, :])) / c[:, None]
+    assert np.max(np.abs(row2 - n[:, 2, :])) <= 1e-15
+    u = n / c[:, None, None]
+    u01, u02, u10 = u[:, 0, 1], u[:, 0, 2], u[:, 1, 0]
+    nn = np.abs(u01) ** 2 + np.abs(u02) ** 2
+    u00 = np.sqrt(1 - nn) * np.exp(1j * np.angle(u[:, 0, 0]))
+    u20 = np.sqrt(nn - np.abs(u10) ** 2) * np.exp(1j * np.angle(u[:, 2, 0]))
+    cj = np.conj
+    rebuilt = np.empty_like(u)
+    rebuilt[:, 0] = np.stack([u00, u01, u02], -1)
+    rebuilt[:, 1] = np.stack([u10, -(cj(u20 * u02) + cj(u00) * u01 * u10) / nn,
+                              (cj(u01 * u20) - cj(u00) * u02 * u10) / nn], -1)
+    rebuilt[:, 2] = np.stack([u20, (cj(u10 * u02) - cj(u00) * u01 * u20) / nn,
+                              -(cj(u01 * u10) + cj(u00) * u02 * u20) / nn], -1)
+    assert np.max(np.abs(rebuilt * c[:, None, None] - n)) <= 1e-12 / 24

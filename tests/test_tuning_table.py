@@ -22,7 +22,7 @@ def test_shipped_tuning_table_format():
         assert 1 <= n <= 64 and fused in (0, 1)
         assert rt in (1, 2, 4, 8, 16) and spb in (32, 64, 256) and nt in (0, 1)
         assert spb != 32 or (lds in (1, 2) and rt <= 2 and fused == 0)
-        assert 0 <= lds <= 6 and 0 <= xm <= 2 and (xm == 0 or lds > 0)
+        assert 0 <= lds <= 6 and 0 <= xm <= 3 and (xm == 0 or lds > 0)
         assert not (prec == 0 and (rt == 16 or lds >= 4))
         assert ms > 0
         key = (lx, ly, lz, lt, prec, recon, n, fused)

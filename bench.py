@@ -260,11 +260,11 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
     def progress(msg):
         print(f"[{tag}] {msg}", file=sys.stderr, flush=True)
 
-    def solve(label, rhs, **kw):
+    def solve(label, rhs, max_iter=60000, **kw):
         progress(f"solve {label}")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        x, info = lat.cg(mass, rhs, tol=tol, max_iter=60000, **kw)
+        x, info = lat.cg(mass, rhs, tol=tol, max_iter=max_iter, **kw)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t
         nr = rhs.shape[0]
@@ -351,9 +351,13 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
         torch.cuda.synchronize()
         v["apply_ms"] = round(e0.elapsed_time(e1) / 5, 3)
         del rv, zv
+        # a network whose flexible CG needs more than 1.5 x the mixed solver's iterations has lost
+        # (and a non-Hermitian direct-form network may converge slowly): the solve stops there and
+        # reports how far it got
+        cap = int(1.5 * out[ref_label]["iters_max"]) if len(variants) > 1 else 60000
         for lp in fcg_link_precs:
             lab = "f16links" if lp == hisq.HISQ_F16 else "f32links"
-            v["fcg_" + lab] = solve(f"fcg_{key}_{lab}", bf, kind=hisq.HISQ_FCG_NN, link_prec=lp)
+            v["fcg_" + lab] = solve(f"fcg_{key}_{lab}", bf, max_iter=cap, kind=hisq.HISQ_FCG_NN, link_prec=lp)
         fbest = min((k for k in v if k.startswith("fcg_")), key=lambda k: v[k]["seconds"])
         v["fcg_best"] = fbest
         v["speedup_vs_mixed"] = round(out[ref_label]["seconds"] / v[fbest]["seconds"], 3)
@@ -538,6 +542,8 @@ def main():
                          "solver comparison at 48^3x12 / 64^3x16 (plain FP64, mixed, learned FCG)")
     ap.add_argument("--epochs", type=int, default=0,
                     help="training epochs of the solver study (0: 20)")
+    ap.add_argument("--fcg-links", default="both", choices=["both", "f32", "f16"],
+                    help="--workload c3|c4: the link copies the flexible CG's inner operator runs with")
     ap.add_argument("--nn-variants", default="",
                     help="solver study: networks to train and solve with, as form:layers pairs, e.g. "
                          "gram:4,gram:2,direct:4 (default gram:4)")
@@ -619,8 +625,9 @@ def main():
         variants = None
         if args.nn_variants:
             variants = [(f.split(":")[0], int(f.split(":")[1])) for f in args.nn_variants.split(",")]
+        links = {"both": None, "f32": (hisq.HISQ_F32,), "f16": (hisq.HISQ_F16,)}[args.fcg_links]
         print(json.dumps(solver_study(args.workload, torch, synth, hisq, pm, epochs=args.epochs,
-                                      variants=variants)))
+                                      fcg_link_precs=links, variants=variants)))
         return
     cfg = synth.WORKLOADS["c1"]
     dims, n = cfg["dims"], args.nrhs
@@ -771,6 +778,17 @@ def main():
         result["dslash_sweep"] = sweep
         del srcs
         result["volume_sweep"] = volume_sweep(hisq, torch, synth, pm)
+        # the same kernel's roofline where no cache level holds the working set (per parity: links
+        # 2.4 GB, input bundle 0.8 GB against the 256 MB last-level cache)
+        big = [e for e in result["volume_sweep"]
+               if e["lattice"] == "64x64x64x16" and e["prec"] == "f32" and e["n"] == 16]
+        if big:
+            e = big[0]
+            result["roofline_64x64x64x16"] = {
+                "bound": "hbm", "achieved": e["compulsory_GBps"], "peak": 8000.0, "unit": "GB/s",
+                "frac": round(e["compulsory_GBps"] / 8000.0, 4),
+                "kernel": "k_dslash_lds (half Dslash, FP32, 16 rhs)", "launch": e["launch"],
+                "counters": "profiles/k_dslash_f32_n16_64x64x64x16.txt"}
 
     if not args.no_cg:
         c2 = synth.WORKLOADS["c2"]

@@ -272,7 +272,8 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
                "iters_mean": round(float(np.mean(info["iters"])), 1),
                "iters_max": max(info["iters"]), "true_resid_max": max(info["true_resid"]),
                "converged": sum(info["converged"]), "fell_back": sum(info["fell_back"]),
-               "reliable_updates": info["reliable_updates"], "rc": info["rc"],
+               "reliable_updates": info["reliable_updates"], "compactions": info["compactions"],
+               "rc": info["rc"],
                "peak_device_GB": round(info["peak_bytes"] / 1e9, 2),
                "fp32_links_from_iter": info["link_switch_iter"],
                "dslash_gflops": round(pm.FLOP_PER_SITE_RHS * info["dslash_site_rhs"] / sec / 1e9, 1)}

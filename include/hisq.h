@@ -219,7 +219,8 @@ typedef struct {
  * is kept separate per rhs so converged rhs can stop).  HISQ_CG_F64 and HISQ_CG_MIXED repack the
  * bundle once a quarter of its slots have finished: finished rhs leave (their solution is written
  * to x), the live ones move to the front, and every later launch works on the smaller bundle
- * with the launch configuration of its size (p->no_compaction = 1 turns this off).  A rhs's
+ * with the launch configuration tuned or stored for its size, else with the one of the size
+ * before the repack (no autotuning inside the solve); p->no_compaction = 1 turns this off.  A rhs's
  * result does not depend on the repacking or on the other rhs of the bundle.
  *   b : device [n][3][V/2] complex128, even sites.   x : device [n][3][V/2] complex128.
  *   HISQ_CG_F64   : FP64 throughout.

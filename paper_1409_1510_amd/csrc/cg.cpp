@@ -150,6 +150,24 @@ int cg_finish(hisq_ctx *ctx, double mass, int n, const void *b, void *x, double 
   return HISQ_OK;
 }
 
+// A bundle that shrinks from n_from to n_to right-hand sides gives (prec, n_to), plain and fused
+// forms, the launch configuration of (prec, n_from) where n_to has none yet, so that the shrunk
+// bundle does not autotune in the middle of the solve (one autotune takes seconds on large
+// lattices).  A configuration that serves n_from rhs serves fewer (the launch only skips the
+// missing rhs); entries n_to already has (tuned, loaded, forced) are kept, and the borrowed ones
+// are not saved by hisq_save_tuning.
+static void borrow_launch(hisq_ctx *ctx, int prec, int n_from, int n_to) {
+  if (n_to < 1 || n_to >= n_from || n_from > HISQ_MAX_RHS) return;
+  for (int e = 0; e < 2; ++e) {
+    TuneEntry &to = ctx->tune[prec][n_to][e];
+    const TuneEntry &from = ctx->tune[prec][n_from][e];
+    if (to.state != TuneEntry::NONE || from.state == TuneEntry::NONE) continue;
+    to.cfg = from.cfg;
+    to.state = TuneEntry::HEURISTIC;
+    to.ms = 0.f;
+  }
+}
+
 // snap_x: optional device [n_snap][n][3][V/2] complex128 receiving x after iterations
 // 0, snap_every, 2 snap_every, ... (plain FP64 solver only); *n_taken = snapshots written.
 int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hisq_cg_params *prm,
@@ -284,6 +302,7 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
       RETCHK(slot_copy(const_cast<void *>(bw), xb1, k, j));
     }
     for (int j = 0; j < m; ++j) map[j] = newmap[j];
+    for (int pr : {HISQ_F64, HISQ_F32, HISQ_F16}) borrow_launch(ctx, pr, ns, m);
     permute_state(*hS, src, m);
     HIPCHK(ctx, hipMemcpyAsync(S, hS, sizeof(CGState), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));  // hS is read and written by the host again

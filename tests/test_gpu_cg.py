@@ -237,6 +237,10 @@ def test_compaction_uneven_bundle_matches_single_solves(kind):
     print(f"kind {kind}: iterations {info['iters']}, repacks {info['compactions']}")
     assert info["compactions"] >= 1
     assert max(info["iters"][:6]) < min(info["iters"][6:])
+    # the shrunk bundle ran with the launch configuration of the full one (no autotune mid-solve)
+    body = hisq.HISQ_F64 if kind == hisq.HISQ_CG_F64 else hisq.HISQ_F32
+    for fused in (0, 1):
+        assert hisq.hisq_get_launch(lat.ctx, body, 2, fused) == hisq.hisq_get_launch(lat.ctx, body, 8, fused)
     res = oracle.true_residual(fat, naik, x.cpu().numpy(), b, dims, mass)
     assert np.all(res <= tol)
     for i in (0, 5, 7):

@@ -570,6 +570,9 @@ def main():
     ap.add_argument("--profile-nn", action="store_true",
                     help="only the learned preconditioner's Gram application at 48^3x12 on 16 rhs, "
                          "2 + --steps times (for a rocprofv3 run)")
+    ap.add_argument("--profile-cg-workload", default="c2", choices=["c2", "c4"],
+                    help="--profile-cg: the 32^3x8 CG to convergence (c2), or --steps iterations of "
+                         "the 64^3x16 mixed CG on 32 rhs (c4)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="short run for rocprofv3: the 32^3x8 mixed CG (FP16 links, 8 rhs) of the "
                          "benchmark, solved twice")
@@ -586,6 +589,34 @@ def main():
     from paper_1409_1510_amd import perfmodel as pm
 
     torch.cuda.set_device(0)
+    if args.profile_cg or args.profile:
+        # counter calibration for the summaries: an elementwise kernel that reads 256 MiB and
+        # writes 256 MiB
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.profile_cg and args.profile_cg_workload == "c4":
+        # the mixed CG's kernels where no cache level holds the vectors: 64^3 x 16, 32 rhs, FP32
+        # links, a fixed number of iterations (tiled links: the per-kernel traffic does not depend
+        # on the link values or on convergence)
+        c4 = synth.WORKLOADS["c4"]
+        fat4, naik4 = synth.tiled_gauge_links(c4["dims"], 7)
+        lat4 = hisq.Lattice(c4["dims"], 0)
+        lat4.load_links(fat4, naik4, hisq.HISQ_LINKS_ALL, 18)
+        del fat4, naik4
+        b = torch.randn(c4["n"], 3, lat4.vh, dtype=torch.complex128, device="cuda:0")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = lat4.cg(c4["mass"], b, tol=1e-12, max_iter=args.steps, kind=hisq.HISQ_CG_MIXED,
+                              link_prec=hisq.HISQ_F32)
+            torch.cuda.synchronize()
+            print(f"profile-cg solve: {time.perf_counter() - t:.3f} s, {max(info['iters'])} iterations "
+                  f"(stopped at the cap), {c4['n']} rhs", flush=True)
+        lat4.close()
+        return
     if args.profile_cg:
         c2 = synth.WORKLOADS["c2"]
         fat2, naik2 = synth.gauge_links(c2["dims"], synth.workload_seed("c2"), eps=c2["eps"])
@@ -667,11 +698,6 @@ def main():
         lat.close()
         return
     if args.profile:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)  # reads 256 MiB, writes 256 MiB
-        torch.cuda.synchronize()
-        del src, dst
         pdims = tuple(int(d) for d in args.profile_dims.split(","))
         prec = hisq.HISQ_F32 if args.profile_prec == "f32" else hisq.HISQ_F16
         if pdims != dims:
@@ -706,6 +732,12 @@ def main():
         return
 
     step = dslash_step(lat, hisq.HISQ_F32, v_e, v_o, w_e, w_o)
+    # context beside the value: the same steps on a device that has been idle for 0.5 s (it takes
+    # ~30 ms of load to reach its sustained speed), 1 warmup step and 10 timed steps
+    torch.cuda.synchronize()
+    time.sleep(0.5)
+    _, ms_idle, _ = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o, 10, 1,
+                                       isolated=False)
     ramp_steps = sustain(torch, step, RAMP_MS)
     ms_step, ms_launch, ms_iso = dslash_step_timing(lat, hisq, torch, hisq.HISQ_F32, v_e, v_o, w_e, w_o,
                                                     args.steps, args.warmup)
@@ -745,6 +777,10 @@ def main():
                      "ms_per_launch_event_bracketed": round(ms_iso, 5)},
         # untimed back-to-back steps before the warmup steps (the device's sustained speed)
         "sustained_load_before_warmup": {"ms": RAMP_MS, "steps": ramp_steps},
+        "from_idle": {"ms_per_launch": round(ms_idle, 5),
+                      "compulsory_GBps": round(bytes_launch / (ms_idle * 1e-3) / 1e9, 1),
+                      "frac_of_peak": round(bytes_launch / (ms_idle * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "note": "10 steps after 0.5 s idle and 1 warmup step, before the sustained load"},
         "gpu_clocks_under_load": clocks,
         # context, not the value: the same launches with each input written by the launch before
         # (D_oe then D_eo of its result, as the CG applies M), where the input is still cached

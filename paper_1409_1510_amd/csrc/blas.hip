@@ -31,13 +31,30 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
+// This thread's share of sum_b row[b] (b = threadIdx.x, threadIdx.x + kThreads, ...), added in
+// ascending b.  The loads are issued eight at a time before their adds, so a long row is not one
+// load latency per element (the summation order, and so every bit of the result, is that of the
+// plain loop).
+__device__ inline double strided_sum(const double *__restrict__ row, int nblk) {
+  double v = 0.0;
+  int b = threadIdx.x;
+  for (; b + 7 * kThreads < nblk; b += 8 * kThreads) {
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = row[b + k * kThreads];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += t[k];
+  }
+  for (; b < nblk; b += kThreads) v += row[b];
+  return v;
+}
+
 // res[row] = sum_b partial[row * nblk + b], rows = n * width.
 __global__ void __launch_bounds__(kThreads)
 k_reduce_rows(const double *__restrict__ partial, int nblk, double *__restrict__ res) {
   __shared__ double red[4];
   const int row = blockIdx.x;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(row) * nblk + b];
+  double v = strided_sum(partial + size_t(row) * nblk, nblk);
   v = block_sum(v, red);
   if (threadIdx.x == 0) res[row] = v;
 }
@@ -98,8 +115,7 @@ __global__ void k_reduce_alpha(const double *__restrict__ partial, int nblk, CGS
   __shared__ double red[4];
   const int r = blockIdx.x;
   if (!S->active[r]) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  double v = strided_sum(partial + size_t(r) * nblk, nblk);
   v = block_sum(v, red);
   if (threadIdx.x == 0) {
     S->pq[r] = v;
@@ -117,8 +133,7 @@ __global__ void k_reduce_beta(const double *__restrict__ partial, int nblk, CGSt
   __shared__ double red[4];
   const int r = blockIdx.x;
   if (!S->active[r]) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  double v = strided_sum(partial + size_t(r) * nblk, nblk);
   v = block_sum(v, red);
   if (threadIdx.x == 0) {
     S->iters[r] += 1;
@@ -260,8 +275,7 @@ __global__ void k_reduce_true(const double *__restrict__ partial, int nblk, CGSt
   __shared__ double red[4];
   const int r = blockIdx.x;
   if (!(final_only ? S->fin[r] : S->sel[r])) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  double v = strided_sum(partial + size_t(r) * nblk, nblk);
   v = block_sum(v, red);
   if (threadIdx.x == 0) {
     S->rr_true[r] = v;
@@ -286,8 +300,7 @@ __global__ void k_reduce_true(const double *__restrict__ partial, int nblk, CGSt
 __global__ void k_init_state(const double *__restrict__ partial, int nblk, CGState *S, int n) {
   __shared__ double red[4];
   const int r = blockIdx.x;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  double v = strided_sum(partial + size_t(r) * nblk, nblk);
   v = block_sum(v, red);
   if (threadIdx.x == 0) {
     S->bnorm2[r] = v;
@@ -315,8 +328,7 @@ __global__ void k_set_rho(const double *__restrict__ partial, int nblk, CGState 
   __shared__ double red[4];
   const int r = blockIdx.x;
   if (!S->sel[r]) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) v += partial[size_t(r) * nblk + b];
+  double v = strided_sum(partial + size_t(r) * nblk, nblk);
   v = block_sum(v, red);
   if (threadIdx.x == 0) {
     S->rho[r] = v;
@@ -357,12 +369,9 @@ __global__ void k_fcg_alpha(const double *__restrict__ pqp, int nblk_pq, const d
   __shared__ double red[4];
   const int r = blockIdx.x;
   if (!S->active[r]) return;
-  double pq = 0.0, pre = 0.0, pim = 0.0;
-  for (int b = threadIdx.x; b < nblk_pq; b += kThreads) pq += pqp[size_t(r) * nblk_pq + b];
-  for (int b = threadIdx.x; b < nblk_pr; b += kThreads) {
-    pre += prp[size_t(2 * r) * nblk_pr + b];
-    pim += prp[size_t(2 * r + 1) * nblk_pr + b];
-  }
+  double pq = strided_sum(pqp + size_t(r) * nblk_pq, nblk_pq);
+  double pre = strided_sum(prp + size_t(2 * r) * nblk_pr, nblk_pr);
+  double pim = strided_sum(prp + size_t(2 * r + 1) * nblk_pr, nblk_pr);
   pq = block_sum(pq, red);
   pre = block_sum(pre, red);
   pim = block_sum(pim, red);
@@ -415,11 +424,8 @@ __global__ void k_fcg_beta(const double *__restrict__ qzp, int nblk, CGState *S)
   __shared__ double red[4];
   const int r = blockIdx.x;
   if (!S->active[r]) return;
-  double re = 0.0, im = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) {
-    re += qzp[size_t(2 * r) * nblk + b];
-    im += qzp[size_t(2 * r + 1) * nblk + b];
-  }
+  double re = strided_sum(qzp + size_t(2 * r) * nblk, nblk);
+  double im = strided_sum(qzp + size_t(2 * r + 1) * nblk, nblk);
   re = block_sum(re, red);
   im = block_sum(im, red);
   if (threadIdx.x == 0) {

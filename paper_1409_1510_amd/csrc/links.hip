@@ -128,8 +128,9 @@ __device__ inline double fit_real_scale(const M3 &m, M3 &rebuilt) {
   return z;
 }
 
-// rows 0, 1; the real z goes to component `half` of the shared scale plane.  Returns the relative
-// error of the reconstructed link (FP64).
+// Rows 0 and 1 into their planes; the real z is returned in *scale (the caller stores the 8 Naik
+// scales of a site two per complex plane).  Returns the relative error of the reconstructed link
+// (FP64).
 template <typename LT>
 __device__ inline double store_r13(LT *__restrict__ dst, int vh, int s, int plane, double *scale, const M3 &m) {
 #pragma unroll

@@ -238,7 +238,9 @@ typedef struct {
  *                   p->link_prec links, FP64 reliable updates); a rhs whose preconditioned step
  *                   breaks down, or whose true residual stops falling (6 replacements in a row
  *                   without a 10 % drop), is finished by MIXED from its current x.
- * Synchronises.  Returns HISQ_ERR_NOCONV if some rhs missed tol within max_iter. */
+ * Synchronises.  Returns HISQ_ERR_NOCONV if some rhs missed tol within max_iter.  With the
+ * environment variable HISQ_CG_TRACE=1, F64/MIXED print one stderr line per residual replacement
+ * of bundle slot 0 (iteration, link copy, true relative residual, true/iterated ratio). */
 int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
                  const hisq_cg_params *p, hisq_cg_stats *stats);
 

@@ -681,6 +681,7 @@ def main():
         torch.cuda.synchronize()
         srcs = {nn: (torch.from_numpy(synth.sources(dims, nn, 9)).to("cuda:0"),
                      torch.from_numpy(synth.sources(dims, nn, 10)).to("cuda:0")) for nn in SWEEP_N}
+        marker = torch.ones(64, device="cuda:0")
         for prec, recon, name in sweep_cases(hisq):
             if recon != 18:
                 lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, recon)
@@ -690,7 +691,11 @@ def main():
                 c, d = torch.empty_like(a), torch.empty_like(b)
                 k = sustain(torch, dslash_step(lat, prec, a, b, c, d), SWEEP_RAMP_MS)
                 dslash_step_timing(lat, hisq, torch, prec, a, b, c, d, 3, 1, isolated=False)
-                # the trace holds 2 k untimed launches, then 2 warmup and 6 timed launches per case
+                # the trace holds, per case, any autotune trials, 2 k untimed launches, 2 warmup and
+                # 6 timed launches, then a marker kernel (a negation of a small tensor) that closes
+                # the case for the summary
+                marker.neg_()
+                torch.cuda.synchronize()
                 print(f"profile-sweep case {name} n {nn} launch {hisq.hisq_get_launch(lat.ctx, prec, nn, 0)} "
                       f"ramp {k}", flush=True)
             if recon != 18:

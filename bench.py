@@ -17,7 +17,8 @@ Also reported on the same JSON line:
   volume_sweep   : the FP32 half Dslash against the lattice volume;
   cg             : seconds per rhs to a true FP64 residual 1e-8 at 32^3 x 8, m = 0.02, 8 rhs, for
                    the mixed-precision solver (FP16 and FP32 links) and the plain FP64 solver;
-  trace_minv     : Tr M^-1 on the same lattice from 64 Z2 noise vectors (Eq. 2), with its error;
+  trace_minv     : Tr M^-1 on the same lattice from 64 Z2 noise vectors (Eq. 2), with its error,
+                   and the chiral condensate (1/V) Tr (m + D)^-1 from 16 of them;
   cg_48x48x48x12 : seconds per rhs to 1e-8 at 48^3 x 12, m = 0.01, 16 Z2 rhs: plain FP64, mixed
                    (FP16 and FP32 links) and the flexible CG with the learned preconditioner,
                    trained here on pairs harvested from plain CG, with iterations and peak memory;
@@ -898,6 +899,12 @@ def main():
             "vectors": nvec, "estimate": round(est, 3), "std_error": round(err, 3),
             "std_error_vs_n": {str(k): round(float(smp[:k].std(ddof=1) / np.sqrt(k)), 3) for k in (16, 32, 64)},
             "seconds": round(sec, 3), "s_per_vector": round(sec / nvec, 5)}
+        # the chiral condensate (1/V) Tr (m + D)^-1 from the library, on the first 16 of the same
+        # noise vectors (one bundle)
+        pbp, pbp_err = lat2.chiral_condensate(c2["mass"], 16, bundle=bundle, seed=synth.workload_seed("c2") + 3,
+                                              kind=hisq.HISQ_CG_MIXED, tol=c2["tol"], link_prec=hisq.HISQ_F16)
+        result["trace_minv"]["chiral_condensate_16_vectors"] = {"estimate": round(pbp, 6),
+                                                                "std_error": round(pbp_err, 6)}
         lat2.close()
 
     if not args.no_c3 and not args.no_cg:

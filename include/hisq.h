@@ -329,6 +329,15 @@ int hisq_z2_noise(hisq_ctx *ctx, unsigned long long seed, long long k0, int n, v
 int hisq_trace_minv(hisq_ctx *ctx, double mass, int n_vec, int bundle, unsigned long long seed,
                     const hisq_cg_params *p, double *samples, double *estimate, double *std_error);
 
+/* The chiral condensate (1/V) Tr (m + D)^-1 of the whole-lattice operator, the trace of Eq. 2
+ * without derivative insertions: the diagonal blocks of (m + D)^-1 are m M_ee^-1 and m M_oo^-1,
+ * and M_oo has the spectrum of M_ee, so it is (2 m / V) Tr M_ee^-1, estimated as hisq_trace_minv
+ * does (same noise vectors, bundles and solver; V the number of sites, taste factors left to the
+ * caller).  estimate (host) is required, std_error (host) may be NULL.  Synchronises; returns
+ * HISQ_ERR_NOCONV, with the estimate still written, if some solve missed tol. */
+int hisq_chiral_condensate(hisq_ctx *ctx, double mass, int n_vec, int bundle, unsigned long long seed,
+                           const hisq_cg_params *p, double *estimate, double *std_error);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dslash import m_ee
+from .dslash import dslash_full, m_ee
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -62,3 +62,28 @@ def trace_samples(fat, naik, dims, mass, seed: int, n_vec: int) -> np.ndarray:
     eta = z2_noise(seed, 0, n_vec, vh).reshape(n_vec, 3 * vh)
     x = np.linalg.solve(m, eta.T).T
     return np.einsum("ki,ki->k", np.conj(eta), x).real
+
+
+def dense_d_full(fat, naik, dims) -> np.ndarray:
+    """D of Eq. 3 on the whole lattice as a dense (3 V) x (3 V) matrix, assembled column by column
+    from dslash_full on unit vectors (component order [site][colour], lexicographic sites)."""
+    vol = int(np.prod(dims))
+    eye = np.eye(3 * vol).reshape(3 * vol, vol, 3)
+    cols = np.stack([dslash_full(fat, naik, e, dims).reshape(3 * vol) for e in eye])
+    return cols.T
+
+
+def chiral_condensate_exact(fat, naik, dims, mass) -> float:
+    """(1/V) Tr (m + D)^-1 over the whole lattice (colour and sites), from the dense inverse of
+    the full operator (small lattices only)."""
+    vol = int(np.prod(dims))
+    a = mass * np.eye(3 * vol) + dense_d_full(fat, naik, dims)
+    return float(np.trace(np.linalg.inv(a)).real) / vol
+
+
+def chiral_condensate_from_trace(trace_minv: float, dims, mass) -> float:
+    """(1/V) Tr (m + D)^-1 from Tr M_ee^-1: the even and odd diagonal blocks of (m + D)^-1 are
+    m M_ee^-1 and m M_oo^-1 (D only connects the parities), and M_oo = m^2 - D_oe D_eo has the
+    spectrum of M_ee (D_eo D_oe and D_oe D_eo share their eigenvalues on equal dimensions), so
+    Tr (m + D)^-1 = 2 m Tr M_ee^-1."""
+    return 2.0 * mass * trace_minv / int(np.prod(dims))

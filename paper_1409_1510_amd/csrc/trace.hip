@@ -93,3 +93,18 @@ extern "C" int hisq_trace_minv(hisq_ctx *ctx, double mass, int n_vec, int bundle
   if (rc_all != HISQ_OK) return set_err(ctx, rc_all, "hisq_trace_minv: some solves missed tol %.3g", p->tol);
   return HISQ_OK;
 }
+
+extern "C" int hisq_chiral_condensate(hisq_ctx *ctx, double mass, int n_vec, int bundle, unsigned long long seed,
+                                      const hisq_cg_params *p, double *estimate, double *std_error) {
+  if (!ctx) return HISQ_ERR_ARG;
+  if (!estimate) return set_err(ctx, HISQ_ERR_ARG, "hisq_chiral_condensate: estimate is required");
+  double t = 0.0, e = 0.0;
+  const int rc = hisq_trace_minv(ctx, mass, n_vec, bundle, seed, p, nullptr, &t, &e);
+  if (rc != HISQ_OK && rc != HISQ_ERR_NOCONV) return rc;
+  // (1/V) Tr (m + D)^-1 = (2 m / V) Tr M_ee^-1 (V = 2 * V/2 sites)
+  const double scale = 2.0 * mass / (2.0 * double(ctx->g.vh));
+  *estimate = scale * t;
+  if (std_error) *std_error = std::fabs(scale) * e;
+  return rc;
+}
+

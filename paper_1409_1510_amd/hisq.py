@@ -137,6 +137,8 @@ def _load():
         "hisq_z2_noise": (cint, [vp, ctypes.c_ulonglong, ctypes.c_longlong, cint, vp]),
         "hisq_trace_minv": (cint, [vp, cd, cint, cint, ctypes.c_ulonglong, ctypes.POINTER(hisq_cg_params),
                                    dp, dp, dp]),
+        "hisq_chiral_condensate": (cint, [vp, cd, cint, cint, ctypes.c_ulonglong,
+                                          ctypes.POINTER(hisq_cg_params), dp, dp]),
         "hisq_nn_save": (cint, [vp, ctypes.c_char_p]),
         "hisq_nn_load": (cint, [vp, ctypes.c_char_p]),
     }
@@ -380,6 +382,16 @@ class Lattice:
         _check(self.ctx, _lib.hisq_trace_minv(self.ctx, mass, n_vec, bundle, seed, ctypes.byref(p), samples,
                                               ctypes.byref(est), ctypes.byref(err)))
         return est.value, err.value, list(samples)
+
+    def chiral_condensate(self, mass, n_vec, bundle=16, seed=1, kind=HISQ_CG_MIXED, tol=1e-8,
+                          max_iter=40000, reliable_every=50, link_prec=HISQ_F32):
+        """(estimate, std_error) of (1/V) Tr (m + D)^-1 from n_vec Z2 noise vectors."""
+        p = hisq_cg_params(kind, tol, max_iter, reliable_every, link_prec, 0, 0)
+        est, err = ctypes.c_double(), ctypes.c_double()
+        hisq_set_stream(self.ctx)
+        _check(self.ctx, _lib.hisq_chiral_condensate(self.ctx, mass, n_vec, bundle, seed, ctypes.byref(p),
+                                                     ctypes.byref(est), ctypes.byref(err)))
+        return est.value, err.value
 
     def cg(self, mass, b, kind=HISQ_CG_F64, tol=1e-10, max_iter=20000, reliable_every=50,
            link_prec=HISQ_F32, x0=None, check_every=0, compaction=True):

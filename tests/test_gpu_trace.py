@@ -1,6 +1,6 @@
 """GPU stochastic trace of M^-1 (Section 1, Eq. 2) against the oracle: the counter-based Z2 noise
-bit for bit, the per-vector samples eta^dag M^-1 eta against dense solves, independence of the
-bundle size, and argument errors."""
+bit for bit, the per-vector samples eta^dag M^-1 eta against dense solves, the chiral condensate
+against the dense whole-lattice operator, independence of the bundle size, and argument errors."""
 import numpy as np
 import pytest
 
@@ -32,6 +32,25 @@ def test_samples_match_dense_solves():
     assert abs(err - ref.std(ddof=1) / np.sqrt(24)) <= 1e-6 * err
     exact = otrace.trace_minv_exact(fat, naik, dims, mass)
     print(f"Tr M^-1: estimate {est:.3f} +- {err:.3f}, exact {exact:.3f}")
+    lat.close()
+
+
+def test_chiral_condensate_matches_the_dense_full_operator():
+    """The GPU chiral condensate is (2m/V) times the GPU trace estimate from the same noise, and
+    it agrees with (1/V) Tr (m + D)^-1 of the oracle's dense whole-lattice operator within the
+    estimator's statistical error (Z2 noise, 4^4, two masses)."""
+    dims = (4, 4, 4, 4)
+    lat, fat, naik = make_lattice(dims, 503)
+    vol = int(np.prod(dims))
+    for mass in (0.3, 2.5):
+        kw = dict(bundle=16, seed=11, kind=hisq.HISQ_CG_F64, tol=1e-12)
+        est, err = lat.chiral_condensate(mass, 256, **kw)
+        tr, tr_err, _ = lat.trace_minv(mass, 256, **kw)
+        assert abs(est - 2 * mass / vol * tr) <= 1e-13 * abs(est)
+        assert abs(err - 2 * mass / vol * tr_err) <= 1e-13 * abs(err)
+        exact = otrace.chiral_condensate_exact(fat, naik, dims, mass)
+        print(f"m={mass}: condensate {est:.6f} +- {err:.6f}, dense {exact:.6f}")
+        assert abs(est - exact) <= 5 * err
     lat.close()
 
 

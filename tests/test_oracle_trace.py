@@ -45,3 +45,19 @@ def test_estimator_is_unbiased_with_the_z2_variance():
     np.fill_diagonal(off, 0.0)
     var = 2 * np.sum(off ** 2)
     assert abs(s.var(ddof=1) / var - 1) < 0.15, (s.var(ddof=1), var)
+
+
+def test_chiral_condensate_from_the_even_odd_trace():
+    """(1/V) Tr (m + D)^-1 of the whole-lattice operator, assembled densely from Eq. 3 and
+    inverted, equals (2m/V) Tr M_ee^-1 of the even-odd operator: pins the even-odd reduction
+    (parity blocks, the sign of M = m^2 - D_eo D_oe, the odd block sharing the even block's
+    spectrum) against an operator assembled independently of M, at two masses on random links,
+    on 4^4 (where hops alias) and on 6 x 4 x 4 x 4."""
+    for dims, seed in (((4, 4, 4, 4), 93), ((6, 4, 4, 4), 94)):
+        fat, naik = synth.gauge_links(dims, seed)
+        for mass in (0.3, 2.5):
+            full = trace.chiral_condensate_exact(fat, naik, dims, mass)
+            eo = trace.chiral_condensate_from_trace(trace.trace_minv_exact(fat, naik, dims, mass), dims, mass)
+            assert abs(full - eo) <= 1e-10 * abs(full), (dims, mass, full, eo)
+            # a dropped factor 2 (only the even block) or m (the block is m M^-1, not M^-1) fails
+            assert abs(full - eo / 2) > 0.1 * abs(full) and abs(full - eo / mass) > 0.1 * abs(full)

@@ -412,7 +412,9 @@ def _host_cores() -> int:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(16, n))  # the GPU machine's share of host cores is 16
+    # one GPU's share of a shared host is 16 CPUs on the machines this runs on, whatever the
+    # affinity mask reports
+    return max(1, min(16, n))
 
 
 _CPU = {}

@@ -452,12 +452,12 @@ def _cpu_cg(job):
     return int(it[0]), time.perf_counter() - t, float(res[0])
 
 
-def cpu_baseline(dims, nrhs, gpu_cg_iters):
+def cpu_baseline(dims, nrhs, gpu_cg_iters, gpu_c3_iters=None):
     """The FP64 numpy oracle timed on the host's cores (a process per core, one thread each):
     the whole-lattice Dslash of the benchmark step (Eq. 3 on both parities, 1146 flop per site and
     rhs) over the benchmark's rhs, the oracle CG on the 8^4 workload solved in full, and the
-    oracle CG on the 32^3 x 8 workload per rhs, extrapolated from a timed sample of iterations to
-    the iteration count of the GPU's plain FP64 solve."""
+    oracle CG on the 32^3 x 8 and 48^3 x 12 workloads per rhs, extrapolated from a timed sample
+    of iterations to the iteration count of the GPU's plain FP64 solve."""
     import multiprocessing as mp
     import platform
     from concurrent.futures import ProcessPoolExecutor
@@ -490,16 +490,20 @@ def cpu_baseline(dims, nrhs, gpu_cg_iters):
                          f"one benchmark step per rhs")
         out["dslash_s_per_rhs"] = round(float(np.median(secs)) / reps, 4)
         # 2. oracle CG: 8^4 solved in full; 32^3 x 8 sampled per rhs
-        c0, c2 = synth.WORKLOADS["c0"], synth.WORKLOADS["c2"]
+        c0, c2, c3 = synth.WORKLOADS["c0"], synth.WORKLOADS["c2"], synth.WORKLOADS["c3"]
         with ProcessPoolExecutor(1, mp_context=ctx, initializer=_cpu_init,
                                  initargs=(c0["dims"], synth.workload_seed("c0"), 1)) as ex0, \
                 ProcessPoolExecutor(2, mp_context=ctx, initializer=_cpu_init,
-                                    initargs=(c2["dims"], synth.workload_seed("c2"), 2)) as ex2:
+                                    initargs=(c2["dims"], synth.workload_seed("c2"), 2)) as ex2, \
+                ProcessPoolExecutor(1, mp_context=ctx, initializer=_cpu_init,
+                                    initargs=(c3["dims"], synth.workload_seed("c3"), 1)) as ex3:
             f0 = ex0.submit(_cpu_cg, (0, c0["mass"], c0["tol"], 100000))
-            k = 8
+            k, k3 = 8, 2
             f2 = [ex2.submit(_cpu_cg, (i, c2["mass"], c2["tol"], k)) for i in range(2)]
+            f3 = ex3.submit(_cpu_cg, (0, c3["mass"], c3["tol"], k3))
             it0, s0, r0 = f0.result()
             samples = [f.result() for f in f2]
+            sample3 = f3.result()
         out["cg_8x8x8x8"] = {"iters": it0, "seconds": round(s0, 3), "true_resid": r0, "tol": c0["tol"],
                              "mass": c0["mass"], "s_per_rhs": round(s0, 3)}
         # k iterations plus the initial and the final residual: k + 2 applications of M
@@ -511,6 +515,14 @@ def cpu_baseline(dims, nrhs, gpu_cg_iters):
             c2_out["gpu_plain_f64_iterations"] = gpu_cg_iters
             c2_out["s_per_rhs_extrapolated"] = round(s_it * gpu_cg_iters, 1)
         out["cg_32x32x32x8_per_rhs"] = c2_out
+        s_it3 = sample3[1] / (k3 + 2)
+        c3_out = {"sample": f"{k3} CG iterations on 1 rhs (one process), plus the initial and final "
+                            "residual: s per iteration = time / (k + 2)",
+                  "s_per_iteration": round(s_it3, 4), "mass": c3["mass"], "tol": c3["tol"]}
+        if gpu_c3_iters:
+            c3_out["gpu_plain_f64_iterations"] = gpu_c3_iters
+            c3_out["s_per_rhs_extrapolated"] = round(s_it3 * gpu_c3_iters, 1)
+        out["cg_48x48x48x12_per_rhs"] = c3_out
         out["host"] = {"cores_used": cores, "os_cpu_count": os.cpu_count(), "machine": platform.machine(),
                        "cpu_model": _cpu_model()}
     finally:
@@ -921,7 +933,10 @@ def main():
         cg_iters = None
         if "cg" in result:
             cg_iters = result["cg"]["plain_f64"]["iters_max"]
-        result["cpu_baseline"] = cpu_baseline(dims, n, cg_iters)
+        c3_iters = None
+        if "cg_48x48x48x12" in result and "plain_f64" in result["cg_48x48x48x12"]:
+            c3_iters = result["cg_48x48x48x12"]["plain_f64"]["iters_max"]
+        result["cpu_baseline"] = cpu_baseline(dims, n, cg_iters, c3_iters)
     lat.close()
     print(json.dumps(result))
 

@@ -119,6 +119,7 @@ __global__ void k_reduce_alpha(const double *__restrict__ partial, int nblk, CGS
   v = block_sum(v, red);
   if (threadIdx.x == 0) {
     S->pq[r] = v;
+    S->rho_prev[r] = S->rho[r];
     if (!(v > 0.0) || !isfinite(v)) {  // M is HPD: <p, Mp> <= 0 means breakdown
       S->alpha[r] = 0.0;
       S->status[r] = CG_BREAKDOWN;
@@ -189,6 +190,60 @@ k_update_px(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p, uns
   using R = decltype(C{}.x);
   using RX = decltype(CX{}.x);
   const R b = R(S->beta[r]);
+  const RX ax = RX(S->alpha[r]);
+  const size_t off = size_t(r) * len;
+  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    unsigned j = base + k * kThreads;
+    if (j < len) {
+      C pj = p[off + j], rj = rv[off + j];
+      CX xj = x[off + j];
+      xj.x = fma(ax, RX(pj.x), xj.x);
+      xj.y = fma(ax, RX(pj.y), xj.y);
+      x[off + j] = xj;
+      pj.x = fma(b, pj.x, rj.x);
+      pj.y = fma(b, pj.y, rj.y);
+      p[off + j] = pj;
+    }
+  }
+}
+
+// k_update_px with the beta reduction of k_reduce_beta done by every workgroup of the rhs (the
+// same partials in the same order, so every workgroup and the separate kernel get the same bits).
+// The first workgroup of a rhs records what k_reduce_beta records; the others read only the
+// iteration's snapshot rho_prev, which no workgroup writes here.  A non-finite ||r||^2 is seen by
+// every workgroup alike: none updates, and the first marks the breakdown.
+template <typename C, typename CX>
+__global__ void __launch_bounds__(kThreads)
+k_update_px_beta(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p, unsigned len, CGState *S,
+                 const double *__restrict__ partial, int nblk, double tol2) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  double v = strided_sum(partial + size_t(r) * nblk, nblk);
+  v = block_sum(v, red);
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!isfinite(v)) {
+    if (first) {
+      S->iters[r] += 1;
+      S->beta[r] = 0.0;
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+    }
+    return;
+  }
+  const double beta = v / S->rho_prev[r];
+  if (first) {
+    S->iters[r] += 1;
+    S->beta[r] = beta;
+    S->rho[r] = v;
+    S->rr[r] = v;
+    if (v <= tol2 * S->bnorm2[r]) S->hit[r] = 1;
+  }
+  using R = decltype(C{}.x);
+  using RX = decltype(CX{}.x);
+  const R b = R(beta);
   const RX ax = RX(S->alpha[r]);
   const size_t off = size_t(r) * len;
   const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
@@ -613,6 +668,35 @@ int cg_update_px(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r,
     k_update_px<float2, float2><<<grid, kThreads, 0, ctx->stream>>>(
         static_cast<float2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S);
   LAUNCHCHK(ctx, "k_update_px");
+  return HISQ_OK;
+}
+
+// Fold the beta reduction into the p/x pass while every workgroup's share of redundant partial
+// reads stays small: nblk workgroups x nblk partials per rhs <= 2^20 (lattices up to V/2 ~ 350 k
+// sites; 32^3 x 8 has 384 of each).
+bool cg_fuse_beta(const hisq_ctx *ctx) {
+  const long long nb = blas_nblk(ctx);
+  return nb * nb <= (1ll << 20);
+}
+
+int cg_update_px_beta(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, CGState *S, int n,
+                      const double *partial, double tol2) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  dim3 grid(nblk, n);
+  if (body_prec == HISQ_F64)
+    k_update_px_beta<double2, double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(x), static_cast<const double2 *>(r), static_cast<double2 *>(p), len, S, partial,
+        nblk, tol2);
+  else if (x64)
+    k_update_px_beta<float2, double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S, partial,
+        nblk, tol2);
+  else
+    k_update_px_beta<float2, float2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<float2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S, partial,
+        nblk, tol2);
+  LAUNCHCHK(ctx, "k_update_px_beta");
   return HISQ_OK;
 }
 

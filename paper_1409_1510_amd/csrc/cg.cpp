@@ -179,6 +179,7 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
   int op_prec = mixed ? prm->link_prec : HISQ_F64;
   const size_t vb = size_t(n) * 3 * g.vh * cplx_bytes(body);
   const double tol2 = prm->tol * prm->tol;
+  const bool fuse_beta = cg_fuse_beta(ctx);
   const int check_every = prm->check_every > 0 ? prm->check_every : 8;
   const int reliable_every = prm->reliable_every > 0 ? prm->reliable_every : 50;
   Vecs v;
@@ -346,8 +347,12 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
     RETCHK(cg_apply_op(ctx, op_prec, mass, ns, v.p, v.t, v.q, partial, &nblk_d, S->active));
     RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, ns));
     RETCHK(cg_update_r(ctx, body, v.r, v.q, S, ns, partial));
-    RETCHK(cg_reduce_beta(ctx, partial, S, ns, tol2));
-    RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns));
+    if (fuse_beta) {
+      RETCHK(cg_update_px_beta(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns, partial, tol2));
+    } else {
+      RETCHK(cg_reduce_beta(ctx, partial, S, ns, tol2));
+      RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns));
+    }
     ++it;
     RETCHK(snapshot());
     if (mixed && it % reliable_every == 0) {

@@ -34,6 +34,7 @@ constexpr double kRateNearTol = 100.0;
 
 struct CGState {
   double rho[HISQ_MAX_RHS];      // <r, r> of the iterated residual (or <z, r> for FCG)
+  double rho_prev[HISQ_MAX_RHS]; // rho as the iteration's alpha reduction read it (for beta)
   double pq[HISQ_MAX_RHS];       // Re <p, M p>
   double alpha[HISQ_MAX_RHS];
   double beta[HISQ_MAX_RHS];
@@ -59,6 +60,13 @@ int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, 
 int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
 int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n, double *partial);
 int cg_update_px(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, const CGState *S, int n);
+// k_reduce_beta folded into k_update_px: every workgroup of a rhs sums that rhs's ||r||^2
+// partials itself (the same fixed order, so the same beta), and the first one records the scalars
+// k_reduce_beta would; used where the partials are few (cg_fuse_beta), as the redundant sums then
+// cost less than a launch.
+bool cg_fuse_beta(const hisq_ctx *ctx);
+int cg_update_px_beta(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, CGState *S, int n,
+                      const double *partial, double tol2);
 int cg_select(hisq_ctx *ctx, CGState *S, int n, int all);
 int cg_accum_x(hisq_ctx *ctx, void *x64, void *xh32, const int *mask, int n);
 int cg_replace_r(hisq_ctx *ctx, int body_prec, const void *b, const void *mx, void *r, void *p,

@@ -86,8 +86,9 @@ int hisq_set_stream(hisq_ctx *ctx, void *hip_stream);
  *   fat, naik : [V][4][3][3] complex128, host or device memory (detected), read only.
  *   copies    : HISQ_LINKS_* mask of device copies to build (FP64 is needed by HISQ_F64 calls
  *               and by the FP64 parts of every solver).
- *   naik_recon: reals stored per Naik link in the FP32 and FP16 copies (Sections 1 and 2 name
- *               the 14- and 9/13-float Naik reconstructions; the FP64 copy always keeps 18):
+ *   naik_recon: reals stored per Naik link in the FP32 and FP16 copies (Section 1 names Naik
+ *               reconstructions from 9 or 13/14 reals, Section 2 uses 14; the FP64 copy always
+ *               keeps 18):
  *               18: all 18 reals;
  *               14: rows 0 and 1 of N plus one complex z, row 2 = z * conj(row0 x row1); exact
  *                   for N = c * U with U in U(3);

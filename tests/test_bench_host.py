@@ -47,3 +47,12 @@ def test_sweep_cases_cover_every_naik_format():
     assert {(p, r) for p, r, _ in cases} == {(0, 18), (1, 18), (1, 14), (1, 13), (1, 9),
                                               (2, 18), (2, 14), (2, 9)}
     assert len({name for _, _, name in cases}) == len(cases)
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py measures one GPU: --gpus N > 1 exits with a message before touching a device."""
+    import subprocess
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0
+    assert "one GPU" in (res.stdout + res.stderr)

@@ -252,3 +252,39 @@ def test_compaction_uneven_bundle_matches_single_solves(kind):
     assert infon["compactions"] == 0 and infon["iters"] == info["iters"]
     assert torch.equal(xn, x)
     lat.close()
+
+
+@pytest.mark.parametrize("kind", [hisq.HISQ_CG_F64, hisq.HISQ_CG_MIXED])
+def test_cg_same_bits_under_every_launch_shape(kind):
+    """A CG solve run with the operator forced to the register-tile form, the LDS form under each
+    XCD map (0-3) and the 32-site form: the solutions and iteration counts agree bit for bit, and
+    every rhs meets tol in the oracle's true residual.  (32, 32, 8, 4) admits every XCD map; half
+    the rhs start from an approximate solution, so the bundle is repacked mid-solve and the shrunk
+    bundles run the forced shape too."""
+    dims, mass, tol, n = (32, 32, 8, 4), 0.1, 1e-8, 4
+    lat, fat, naik = make_lattice(dims, 214)
+    b = synth.sources(dims, n, 215)
+    tb = torch.from_numpy(b).to(DEV)
+    xa, _ = lat.cg(mass, tb, kind=hisq.HISQ_CG_F64, tol=1e-4)
+    x0 = xa.clone()
+    x0[2:] = 0
+    prec = hisq.HISQ_F64 if kind == hisq.HISQ_CG_F64 else hisq.HISQ_F32
+    cfgs = [(2, 64, 0, 0, 0)] + [(1, 64, 1, 1, xm) for xm in range(4)]
+    if prec == hisq.HISQ_F32:
+        cfgs += [(1, 32, 1, 1, 2), (2, 64, 1, 2, 3)]
+    first = None
+    for cfg in cfgs:
+        for m in range(1, n + 1):
+            hisq.hisq_set_launch(lat.ctx, prec, m, cfg)
+        x, info = lat.cg(mass, tb, x0=x0, kind=kind, tol=tol, link_prec=hisq.HISQ_F32)
+        assert info["rc"] == 0, (cfg, info)
+        if first is None:
+            first = (x, info)
+            assert info["compactions"] >= 1
+            res = oracle.true_residual(fat, naik, x.cpu().numpy(), b, dims, mass)
+            assert np.all(res <= tol), res
+        else:
+            assert info["iters"] == first[1]["iters"], cfg
+            assert torch.equal(x, first[0]), cfg
+    print(f"kind {kind}: {len(cfgs)} launch shapes, iterations {first[1]['iters']}")
+    lat.close()

@@ -241,7 +241,11 @@ typedef struct {
  *                   without a 10 % drop), is finished by MIXED from its current x.
  * Synchronises.  Returns HISQ_ERR_NOCONV if some rhs missed tol within max_iter.  With the
  * environment variable HISQ_CG_TRACE=1, F64/MIXED print one stderr line per residual replacement
- * of bundle slot 0 (iteration, link copy, true relative residual, true/iterated ratio). */
+ * of bundle slot 0 (iteration, link copy, true relative residual, true/iterated ratio).  The
+ * F64/MIXED iteration sums the per-rhs alpha partials inside the r pass for V/2 up to ~150 k
+ * sites and the beta partials inside the p/x pass for V/2 up to ~350 k (32^3 x 8, V/2 = 131 k:
+ * both, four launches per iteration); HISQ_CG_FUSED_REDUCTIONS=0 keeps those sums as launches of
+ * their own, with the same bits. */
 int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
                  const hisq_cg_params *p, hisq_cg_stats *stats);
 

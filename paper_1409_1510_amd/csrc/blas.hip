@@ -151,16 +151,12 @@ __global__ void k_reduce_beta(const double *__restrict__ partial, int nblk, CGSt
   }
 }
 
-// r -= alpha q and the partials of ||r||^2 (the solution update is left to k_update_px)
+// r -= a q for rhs r and this workgroup's partial of ||r||^2
 template <typename C>
-__global__ void __launch_bounds__(kThreads)
-k_update_r(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, const CGState *S,
-           double *__restrict__ partial) {
-  __shared__ double red[4];
-  const int r = blockIdx.y;
-  if (!S->active[r]) return;
+__device__ inline void update_r_body(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, int r,
+                                     double alpha, double *__restrict__ partial, double *red) {
   using R = decltype(C{}.x);
-  const R a = R(S->alpha[r]);
+  const R a = R(alpha);
   const size_t off = size_t(r) * len;
   double rr = 0.0;
   const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
@@ -178,6 +174,46 @@ k_update_r(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, 
   }
   rr = block_sum(rr, red);
   if (threadIdx.x == 0) partial[size_t(r) * nblk + blockIdx.x] = rr;
+}
+
+// r -= alpha q and the partials of ||r||^2 (the solution update is left to k_update_px)
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_update_r(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, const CGState *S,
+           double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  update_r_body(rv, q, len, nblk, r, S->alpha[r], partial, red);
+}
+
+// k_update_r with the alpha reduction of k_reduce_alpha done by every workgroup of the rhs: the
+// same <p, Mp> partials summed in the same order, so every workgroup and the separate kernel get
+// the same alpha.  The first workgroup of a rhs records what k_reduce_alpha records; no workgroup
+// reads those fields here.  A breakdown (<p, Mp> <= 0 or not finite) is seen by every workgroup
+// alike: none updates, and the first deactivates the rhs.  The ||r||^2 partials go to a buffer
+// apart from the <p, Mp> ones, which other workgroups may still be reading.
+template <typename C>
+__global__ void __launch_bounds__(kThreads)
+k_update_r_alpha(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, CGState *S,
+                 const double *__restrict__ pq_partial, int nblk_pq, double *__restrict__ partial) {
+  __shared__ double red[4];
+  const int r = blockIdx.y;
+  if (!S->active[r]) return;
+  double v = strided_sum(pq_partial + size_t(r) * nblk_pq, nblk_pq);
+  v = block_sum(v, red);
+  const bool ok = v > 0.0 && isfinite(v);  // M is HPD: <p, Mp> <= 0 means breakdown
+  const double alpha = ok ? S->rho[r] / v : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->pq[r] = v;
+    S->rho_prev[r] = S->rho[r];
+    S->alpha[r] = alpha;
+    if (!ok) {
+      S->status[r] = CG_BREAKDOWN;
+      S->active[r] = 0;
+    }
+  }
+  if (ok) update_r_body(rv, q, len, nblk, r, alpha, partial, red);
 }
 
 // x += alpha p; p = r + beta p: the solution update of the step, deferred to the pass that
@@ -652,6 +688,31 @@ int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S
     k_update_r<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<float2 *>(r), static_cast<const float2 *>(q),
                                                            len, nblk, S, partial);
   LAUNCHCHK(ctx, "k_update_r");
+  return HISQ_OK;
+}
+
+// Fold the alpha reduction into the r pass under the same rule: nblk workgroups x the Dslash's
+// partials per rhs <= 2^20 (32^3 x 8: 384 x 2048).
+bool cg_fuse_alpha(const hisq_ctx *ctx) {
+  return (long long)blas_nblk(ctx) * dslash_partials(ctx->g) <= (1ll << 20);
+}
+
+size_t cg_partial_doubles(const hisq_ctx *ctx, int n) {
+  return size_t(n) * (size_t(dslash_partials(ctx->g)) + size_t(blas_nblk(ctx)));
+}
+
+int cg_update_r_alpha(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n,
+                      const double *pq_partial, int nblk_pq, double *partial) {
+  const unsigned len = 3u * ctx->g.vh;
+  const int nblk = blas_nblk(ctx);
+  dim3 grid(nblk, n);
+  if (body_prec == HISQ_F64)
+    k_update_r_alpha<double2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<double2 *>(r), static_cast<const double2 *>(q), len, nblk, S, pq_partial, nblk_pq, partial);
+  else
+    k_update_r_alpha<float2><<<grid, kThreads, 0, ctx->stream>>>(
+        static_cast<float2 *>(r), static_cast<const float2 *>(q), len, nblk, S, pq_partial, nblk_pq, partial);
+  LAUNCHCHK(ctx, "k_update_r_alpha");
   return HISQ_OK;
 }
 

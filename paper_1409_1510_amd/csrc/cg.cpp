@@ -37,6 +37,13 @@ bool cg_trace() {
   return on;
 }
 
+// HISQ_CG_FUSED_REDUCTIONS=0 keeps the alpha and beta reductions as launches of their own on
+// every lattice (read at each solve; the results are the same bits either way).
+bool fused_reductions() {
+  const char *e = getenv("HISQ_CG_FUSED_REDUCTIONS");
+  return !(e && e[0] == '0' && e[1] == 0);
+}
+
 // What the final residual needs of a rhs that left the bundle.
 struct SlotRecord {
   int iters = 0, replacements = 0, status = 0;
@@ -179,7 +186,10 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
   int op_prec = mixed ? prm->link_prec : HISQ_F64;
   const size_t vb = size_t(n) * 3 * g.vh * cplx_bytes(body);
   const double tol2 = prm->tol * prm->tol;
-  const bool fuse_beta = cg_fuse_beta(ctx);
+  const bool fuse_beta = fused_reductions() && cg_fuse_beta(ctx);
+  const bool fuse_alpha = fused_reductions() && cg_fuse_alpha(ctx);
+  // the r pass's ||r||^2 partials, apart from the <p, Mp> partials when it also sums those
+  double *rr_partial = fuse_alpha ? partial + size_t(n) * dslash_partials(g) : partial;
   const int check_every = prm->check_every > 0 ? prm->check_every : 8;
   const int reliable_every = prm->reliable_every > 0 ? prm->reliable_every : 50;
   Vecs v;
@@ -345,12 +355,16 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
   while (nactive > 0 && it < prm->max_iter) {
     int nblk_d = 0;
     RETCHK(cg_apply_op(ctx, op_prec, mass, ns, v.p, v.t, v.q, partial, &nblk_d, S->active));
-    RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, ns));
-    RETCHK(cg_update_r(ctx, body, v.r, v.q, S, ns, partial));
-    if (fuse_beta) {
-      RETCHK(cg_update_px_beta(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns, partial, tol2));
+    if (fuse_alpha) {
+      RETCHK(cg_update_r_alpha(ctx, body, v.r, v.q, S, ns, partial, nblk_d, rr_partial));
     } else {
-      RETCHK(cg_reduce_beta(ctx, partial, S, ns, tol2));
+      RETCHK(cg_reduce_alpha(ctx, partial, nblk_d, S, ns));
+      RETCHK(cg_update_r(ctx, body, v.r, v.q, S, ns, rr_partial));
+    }
+    if (fuse_beta) {
+      RETCHK(cg_update_px_beta(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns, rr_partial, tol2));
+    } else {
+      RETCHK(cg_reduce_beta(ctx, rr_partial, S, ns, tol2));
       RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns));
     }
     ++it;
@@ -488,8 +502,7 @@ extern "C" int hisq_cg_mrhs(hisq_ctx *ctx, double mass, int n, const void *b, vo
   auto t0 = std::chrono::steady_clock::now();
   void *sp, *pp, *hp;
   RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));
-  const int nblk_max = std::max(blas_nblk(ctx), dslash_partials(ctx->g));
-  RETCHK(ws_get(ctx, WS_PARTIAL, size_t(n) * nblk_max * sizeof(double), &pp));
+  RETCHK(ws_get(ctx, WS_PARTIAL, cg_partial_doubles(ctx, n) * sizeof(double), &pp));
   RETCHK(pinned_get(ctx, sizeof(CGState), &hp));
   CGState *S = static_cast<CGState *>(sp);
   CGState *hS = static_cast<CGState *>(hp);
@@ -518,8 +531,7 @@ extern "C" int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b,
   const size_t vbytes = size_t(n) * 3 * g.vh * 16;
   void *sp, *pp, *hp, *xstar, *t64;
   RETCHK(ws_get(ctx, WS_SCAL, sizeof(CGState), &sp));
-  const int nblk_max = std::max(blas_nblk(ctx), dslash_partials(ctx->g));
-  RETCHK(ws_get(ctx, WS_PARTIAL, size_t(n) * nblk_max * sizeof(double), &pp));
+  RETCHK(ws_get(ctx, WS_PARTIAL, cg_partial_doubles(ctx, n) * sizeof(double), &pp));
   RETCHK(pinned_get(ctx, sizeof(CGState), &hp));
   RETCHK(ws_get(ctx, WS_CG7, vbytes, &xstar));
   CGState *S = static_cast<CGState *>(sp);

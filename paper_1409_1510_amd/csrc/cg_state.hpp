@@ -59,6 +59,15 @@ int blas_nblk(const hisq_ctx *ctx);
 int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n);
 int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
 int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n, double *partial);
+// k_reduce_alpha folded into k_update_r the same way (cg_fuse_alpha): every workgroup of a rhs
+// sums its <p, Mp> partials (pq_partial, nblk_pq per rhs) and the ||r||^2 partials go to
+// `partial`, which must not overlap pq_partial.
+bool cg_fuse_alpha(const hisq_ctx *ctx);
+int cg_update_r_alpha(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n,
+                      const double *pq_partial, int nblk_pq, double *partial);
+// Size of the CG's partials buffer in doubles: the Dslash's <p, Mp> partials and, after them,
+// the BLAS kernels' partials, for n rhs.
+size_t cg_partial_doubles(const hisq_ctx *ctx, int n);
 int cg_update_px(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, const CGState *S, int n);
 // k_reduce_beta folded into k_update_px: every workgroup of a rhs sums that rhs's ||r||^2
 // partials itself (the same fixed order, so the same beta), and the first one records the scalars

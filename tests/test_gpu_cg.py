@@ -288,3 +288,30 @@ def test_cg_same_bits_under_every_launch_shape(kind):
             assert torch.equal(x, first[0]), cfg
     print(f"kind {kind}: {len(cfgs)} launch shapes, iterations {first[1]['iters']}")
     lat.close()
+
+
+@pytest.mark.parametrize("kind", [hisq.HISQ_CG_F64, hisq.HISQ_CG_MIXED])
+def test_fused_reductions_same_bits(kind, monkeypatch):
+    """The alpha and beta sums done inside the r and p/x passes (every workgroup of a rhs sums
+    the partials itself) against the separate reduction launches: the same solutions and
+    iteration counts bit for bit, through a repack of the bundle.  At 16^3 x 8 both are fused."""
+    dims, mass, tol, n = (16, 16, 16, 8), 0.05, 1e-8, 4
+    lat, fat, naik = make_lattice(dims, 216)
+    b = synth.sources(dims, n, 217)
+    tb = torch.from_numpy(b).to(DEV)
+    xa, _ = lat.cg(mass, tb, kind=hisq.HISQ_CG_F64, tol=1e-4)
+    x0 = xa.clone()
+    x0[2:] = 0
+    kw = dict(x0=x0, kind=kind, tol=tol, link_prec=hisq.HISQ_F16)
+    monkeypatch.setenv("HISQ_CG_FUSED_REDUCTIONS", "0")
+    xs, infos = lat.cg(mass, tb, **kw)
+    monkeypatch.delenv("HISQ_CG_FUSED_REDUCTIONS")
+    xf, infof = lat.cg(mass, tb, **kw)
+    assert infos["rc"] == 0 and infof["rc"] == 0
+    assert infof["compactions"] >= 1
+    assert infof["iters"] == infos["iters"]
+    assert torch.equal(xf, xs)
+    res = oracle.true_residual(fat, naik, xf.cpu().numpy(), b, dims, mass)
+    assert np.all(res <= tol), res
+    print(f"kind {kind}: iterations {infof['iters']}")
+    lat.close()

@@ -423,6 +423,32 @@ def test_full_size_48c12_64c16_sampled_sites(name, prec, n):
     lat.close()
 
 
+@pytest.mark.parametrize("name,prec,n,recon", [("c4", hisq.HISQ_F32, 32, 14), ("c4", hisq.HISQ_F16, 32, 9),
+                                               ("c3", hisq.HISQ_F32, 16, 9), ("c3", hisq.HISQ_F16, 16, 13)])
+def test_full_size_compressed_naik_sampled_sites(name, prec, n, recon):
+    """Naik links stored as 14, 13 or 9 reals at 48^3 x 12 and 64^3 x 16, in an LDS launch under
+    the lattice's XCD map (z slabs at 48^3 x 12, z-tiled y slabs at 64^3 x 16): sampled output
+    sites against the per-site oracle on the full (uncompressed) gauge-rotated links, so every
+    reconstruction is checked at the full volume."""
+    dims = synth.WORKLOADS[name]["dims"]
+    fat, naik = _rotated_tiled_links(dims)
+    lat = hisq.Lattice(dims, 0)
+    lat.load_links(fat, naik, hisq.HISQ_LINKS_F32 | hisq.HISQ_LINKS_F16, recon)
+    cfg = (2, 64, 1, 2, 3 if name == "c4" else 1)
+    hisq.hisq_set_launch(lat.ctx, prec, n, cfg)
+    rng = np.random.default_rng(7)
+    sites = np.concatenate([[0, 1, lat.vh - 1], rng.choice(lat.vh, 40, replace=False)])
+    v = synth.sources(dims, n, 133)
+    tv = torch.from_numpy(v).to(DEV).to(torch.complex64)
+    for par in (0, 1):
+        ref = oracle.dslash_sites(fat, naik, v, dims, par, sites)
+        got = lat.dslash(par, prec, tv).cpu().numpy()[:, :, sites]
+        err = rel_l2(got, ref)
+        print(f"{name} prec {prec} r{recon} parity {par}: rel L2 {err:.3g}")
+        assert err <= (2e-3 if prec == hisq.HISQ_F16 else 1e-6)
+    lat.close()
+
+
 def test_tuning_table_round_trip(tmp_path):
     """Tuned choices saved to a table are taken back by a new context on the same lattice and link
     formats; the file keeps other lattices' entries, and lines with an invalid configuration or

@@ -31,6 +31,29 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
+// Complex loads and stores with the non-temporal hint, for operands a pass touches for the last
+// time before the next Dslash pair: they should not push the links and the Dslash's input out of
+// the caches (the same values, so the same bits).
+template <typename C>
+__device__ inline C load_nt(const C *p) {
+  using R = decltype(C{}.x);
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+  C c;
+  c.x = v.x;
+  c.y = v.y;
+  return c;
+}
+template <typename C>
+__device__ inline void store_nt(C *p, C c) {
+  using R = decltype(C{}.x);
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = c.x;
+  v.y = c.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+}
+
 // This thread's share of sum_b row[b] (b = threadIdx.x, threadIdx.x + kThreads, ...), added in
 // ascending b.  The loads are issued eight at a time before their adds, so a long row is not one
 // load latency per element (the summation order, and so every bit of the result, is that of the
@@ -164,7 +187,7 @@ __device__ inline void update_r_body(C *__restrict__ rv, const C *__restrict__ q
   for (int k = 0; k < kItems; ++k) {
     unsigned j = base + k * kThreads;
     if (j < len) {
-      C qj = q[off + j], rj = rv[off + j];
+      C qj = load_nt(q + off + j), rj = rv[off + j];
       rj.x = fma(-a, qj.x, rj.x);
       rj.y = fma(-a, qj.y, rj.y);
       rv[off + j] = rj;
@@ -234,10 +257,10 @@ k_update_px(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p, uns
     unsigned j = base + k * kThreads;
     if (j < len) {
       C pj = p[off + j], rj = rv[off + j];
-      CX xj = x[off + j];
+      CX xj = load_nt(x + off + j);
       xj.x = fma(ax, RX(pj.x), xj.x);
       xj.y = fma(ax, RX(pj.y), xj.y);
-      x[off + j] = xj;
+      store_nt(x + off + j, xj);
       pj.x = fma(b, pj.x, rj.x);
       pj.y = fma(b, pj.y, rj.y);
       p[off + j] = pj;
@@ -288,10 +311,10 @@ k_update_px_beta(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p
     unsigned j = base + k * kThreads;
     if (j < len) {
       C pj = p[off + j], rj = rv[off + j];
-      CX xj = x[off + j];
+      CX xj = load_nt(x + off + j);
       xj.x = fma(ax, RX(pj.x), xj.x);
       xj.y = fma(ax, RX(pj.y), xj.y);
-      x[off + j] = xj;
+      store_nt(x + off + j, xj);
       pj.x = fma(b, pj.x, rj.x);
       pj.y = fma(b, pj.y, rj.y);
       p[off + j] = pj;

@@ -588,6 +588,9 @@ def main():
     ap.add_argument("--profile-cg-workload", default="c2", choices=["c2", "c4"],
                     help="--profile-cg: the 32^3x8 CG to convergence (c2), or --steps iterations of "
                          "the 64^3x16 mixed CG on 32 rhs (c4)")
+    ap.add_argument("--cg-naik-recon", type=int, default=18, choices=[18, 14, 13, 9],
+                    help="reals per stored Naik link of the FP32 and FP16 copies in the 32^3x8 CG "
+                         "(default run and --profile-cg)")
     ap.add_argument("--profile-cg", action="store_true",
                     help="short run for rocprofv3: the 32^3x8 mixed CG (FP16 links, 8 rhs) of the "
                          "benchmark, solved twice")
@@ -636,7 +639,7 @@ def main():
         c2 = synth.WORKLOADS["c2"]
         fat2, naik2 = synth.gauge_links(c2["dims"], synth.workload_seed("c2"), eps=c2["eps"])
         lat2 = hisq.Lattice(c2["dims"], 0)
-        lat2.load_links(fat2, naik2)
+        lat2.load_links(fat2, naik2, hisq.HISQ_LINKS_ALL, args.cg_naik_recon)
         b = torch.from_numpy(synth.sources(c2["dims"], c2["n"], synth.workload_seed("c2") + 1)).to("cuda:0")
         for _ in range(2):
             torch.cuda.synchronize()
@@ -851,9 +854,10 @@ def main():
         c2 = synth.WORKLOADS["c2"]
         fat2, naik2 = synth.gauge_links(c2["dims"], synth.workload_seed("c2"), eps=c2["eps"])
         lat2 = hisq.Lattice(c2["dims"], 0)
-        lat2.load_links(fat2, naik2)
+        lat2.load_links(fat2, naik2, hisq.HISQ_LINKS_ALL, args.cg_naik_recon)
         b = torch.from_numpy(synth.sources(c2["dims"], c2["n"], synth.workload_seed("c2") + 1)).to("cuda:0")
-        cg = {"workload": "32x32x32x8, m=0.02, 8 complex Gaussian rhs, tol 1e-8 (true FP64 residual)"}
+        cg = {"workload": "32x32x32x8, m=0.02, 8 complex Gaussian rhs, tol 1e-8 (true FP64 residual)",
+              "naik_reals": args.cg_naik_recon}
         for name, kw in (("mixed_f16links", dict(kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F16)),
                          ("mixed_f32links", dict(kind=hisq.HISQ_CG_MIXED, link_prec=hisq.HISQ_F32)),
                          ("plain_f64", dict(kind=hisq.HISQ_CG_F64))):

@@ -12,7 +12,9 @@
 #include "internal.hpp"
 #include "cg_state.hpp"
 
+#include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 namespace {
 
@@ -174,17 +176,17 @@ __global__ void k_reduce_beta(const double *__restrict__ partial, int nblk, CGSt
   }
 }
 
-// r -= a q for rhs r and this workgroup's partial of ||r||^2
-template <typename C>
+// r -= a q for rhs r and this workgroup's partial of ||r||^2 (ITEMS complex per thread)
+template <int ITEMS, typename C>
 __device__ inline void update_r_body(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, int r,
                                      double alpha, double *__restrict__ partial, double *red) {
   using R = decltype(C{}.x);
   const R a = R(alpha);
   const size_t off = size_t(r) * len;
   double rr = 0.0;
-  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+  const unsigned base = blockIdx.x * (kThreads * ITEMS) + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     unsigned j = base + k * kThreads;
     if (j < len) {
       C qj = load_nt(q + off + j), rj = rv[off + j];
@@ -200,14 +202,14 @@ __device__ inline void update_r_body(C *__restrict__ rv, const C *__restrict__ q
 }
 
 // r -= alpha q and the partials of ||r||^2 (the solution update is left to k_update_px)
-template <typename C>
+template <int ITEMS, typename C>
 __global__ void __launch_bounds__(kThreads)
 k_update_r(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int nblk, const CGState *S,
            double *__restrict__ partial) {
   __shared__ double red[4];
   const int r = blockIdx.y;
   if (!S->active[r]) return;
-  update_r_body(rv, q, len, nblk, r, S->alpha[r], partial, red);
+  update_r_body<ITEMS>(rv, q, len, nblk, r, S->alpha[r], partial, red);
 }
 
 // k_update_r with the alpha reduction of k_reduce_alpha done by every workgroup of the rhs: the
@@ -236,12 +238,12 @@ k_update_r_alpha(C *__restrict__ rv, const C *__restrict__ q, unsigned len, int 
       S->active[r] = 0;
     }
   }
-  if (ok) update_r_body(rv, q, len, nblk, r, alpha, partial, red);
+  if (ok) update_r_body<kItems>(rv, q, len, nblk, r, alpha, partial, red);
 }
 
 // x += alpha p; p = r + beta p: the solution update of the step, deferred to the pass that
 // rewrites p anyway (one read of p instead of two)
-template <typename C, typename CX>
+template <int ITEMS, typename C, typename CX>
 __global__ void __launch_bounds__(kThreads)
 k_update_px(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p, unsigned len, const CGState *S) {
   const int r = blockIdx.y;
@@ -251,9 +253,9 @@ k_update_px(CX *__restrict__ x, const C *__restrict__ rv, C *__restrict__ p, uns
   const R b = R(S->beta[r]);
   const RX ax = RX(S->alpha[r]);
   const size_t off = size_t(r) * len;
-  const unsigned base = blockIdx.x * kPerBlock + threadIdx.x;
+  const unsigned base = blockIdx.x * (kThreads * ITEMS) + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     unsigned j = base + k * kThreads;
     if (j < len) {
       C pj = p[off + j], rj = rv[off + j];
@@ -700,16 +702,33 @@ int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, 
   return HISQ_OK;
 }
 
+// Workgroups of the unfused r and p/x passes take 256 elements each (one per thread) where the
+// beta reduction is not folded into the p/x pass (large lattices): on MI355X a streaming pass
+// over a few hundred MB runs ~10 % faster in workgroups of 256 elements than of 1024 (measured
+// with 2-read 1-write and 3-read 2-write passes at 0.25 and 1.6 GB per operand).  Where it is
+// folded, every workgroup re-reads all partials of its rhs, so the passes keep 1024 elements
+// (and the env switch that unfolds the reductions keeps the same partials, so the same bits).
+static bool fine_passes(const hisq_ctx *ctx) { return !cg_fuse_beta(ctx); }
+
+int cg_pass_nblk(const hisq_ctx *ctx) {
+  return fine_passes(ctx) ? (3 * ctx->g.vh + kThreads - 1) / kThreads : blas_nblk(ctx);
+}
+
 int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n, double *partial) {
   const unsigned len = 3u * ctx->g.vh;
-  const int nblk = blas_nblk(ctx);
+  const int nblk = cg_pass_nblk(ctx);
   dim3 grid(nblk, n);
+  auto go = [&](auto *rr, auto *qq) {
+    using C = std::remove_pointer_t<decltype(rr)>;
+    if (fine_passes(ctx))
+      k_update_r<1, C><<<grid, kThreads, 0, ctx->stream>>>(rr, qq, len, nblk, S, partial);
+    else
+      k_update_r<kItems, C><<<grid, kThreads, 0, ctx->stream>>>(rr, qq, len, nblk, S, partial);
+  };
   if (body_prec == HISQ_F64)
-    k_update_r<double2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<double2 *>(r), static_cast<const double2 *>(q),
-                                                            len, nblk, S, partial);
+    go(static_cast<double2 *>(r), static_cast<const double2 *>(q));
   else
-    k_update_r<float2><<<grid, kThreads, 0, ctx->stream>>>(static_cast<float2 *>(r), static_cast<const float2 *>(q),
-                                                           len, nblk, S, partial);
+    go(static_cast<float2 *>(r), static_cast<const float2 *>(q));
   LAUNCHCHK(ctx, "k_update_r");
   return HISQ_OK;
 }
@@ -721,7 +740,7 @@ bool cg_fuse_alpha(const hisq_ctx *ctx) {
 }
 
 size_t cg_partial_doubles(const hisq_ctx *ctx, int n) {
-  return size_t(n) * (size_t(dslash_partials(ctx->g)) + size_t(blas_nblk(ctx)));
+  return size_t(n) * (size_t(dslash_partials(ctx->g)) + size_t(std::max(blas_nblk(ctx), cg_pass_nblk(ctx))));
 }
 
 int cg_update_r_alpha(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n,
@@ -741,16 +760,21 @@ int cg_update_r_alpha(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGSt
 
 int cg_update_px(hisq_ctx *ctx, int body_prec, bool x64, void *x, const void *r, void *p, const CGState *S, int n) {
   const unsigned len = 3u * ctx->g.vh;
-  dim3 grid(blas_nblk(ctx), n);
+  dim3 grid(cg_pass_nblk(ctx), n);
+  auto go = [&](auto *xx, auto *rr, auto *pp) {
+    using CX = std::remove_pointer_t<decltype(xx)>;
+    using C = std::remove_cv_t<std::remove_pointer_t<decltype(rr)>>;
+    if (fine_passes(ctx))
+      k_update_px<1, C, CX><<<grid, kThreads, 0, ctx->stream>>>(xx, rr, pp, len, S);
+    else
+      k_update_px<kItems, C, CX><<<grid, kThreads, 0, ctx->stream>>>(xx, rr, pp, len, S);
+  };
   if (body_prec == HISQ_F64)
-    k_update_px<double2, double2><<<grid, kThreads, 0, ctx->stream>>>(
-        static_cast<double2 *>(x), static_cast<const double2 *>(r), static_cast<double2 *>(p), len, S);
+    go(static_cast<double2 *>(x), static_cast<const double2 *>(r), static_cast<double2 *>(p));
   else if (x64)
-    k_update_px<float2, double2><<<grid, kThreads, 0, ctx->stream>>>(
-        static_cast<double2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S);
+    go(static_cast<double2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p));
   else
-    k_update_px<float2, float2><<<grid, kThreads, 0, ctx->stream>>>(
-        static_cast<float2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p), len, S);
+    go(static_cast<float2 *>(x), static_cast<const float2 *>(r), static_cast<float2 *>(p));
   LAUNCHCHK(ctx, "k_update_px");
   return HISQ_OK;
 }
@@ -784,8 +808,8 @@ int cg_update_px_beta(hisq_ctx *ctx, int body_prec, bool x64, void *x, const voi
   return HISQ_OK;
 }
 
-int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2) {
-  k_reduce_beta<<<n, kThreads, 0, ctx->stream>>>(partial, blas_nblk(ctx), S, tol2);
+int cg_reduce_beta(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n, double tol2) {
+  k_reduce_beta<<<n, kThreads, 0, ctx->stream>>>(partial, nblk, S, tol2);
   LAUNCHCHK(ctx, "k_reduce_beta");
   return HISQ_OK;
 }

@@ -364,7 +364,7 @@ int cg_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x, const hi
     if (fuse_beta) {
       RETCHK(cg_update_px_beta(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns, rr_partial, tol2));
     } else {
-      RETCHK(cg_reduce_beta(ctx, rr_partial, S, ns, tol2));
+      RETCHK(cg_reduce_beta(ctx, rr_partial, cg_pass_nblk(ctx), S, ns, tol2));
       RETCHK(cg_update_px(ctx, body, !mixed, mixed ? v.xh : xw, v.r, v.p, S, ns));
     }
     ++it;

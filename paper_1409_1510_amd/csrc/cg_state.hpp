@@ -57,7 +57,9 @@ struct CGState {
 struct hisq_ctx;
 int blas_nblk(const hisq_ctx *ctx);
 int cg_reduce_alpha(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n);
-int cg_reduce_beta(hisq_ctx *ctx, const double *partial, CGState *S, int n, double tol2);
+int cg_reduce_beta(hisq_ctx *ctx, const double *partial, int nblk, CGState *S, int n, double tol2);
+// The unfused r pass writes cg_pass_nblk partials per rhs (finer workgroups on large lattices).
+int cg_pass_nblk(const hisq_ctx *ctx);
 int cg_update_r(hisq_ctx *ctx, int body_prec, void *r, const void *q, CGState *S, int n, double *partial);
 // k_reduce_alpha folded into k_update_r the same way (cg_fuse_alpha): every workgroup of a rhs
 // sums its <p, Mp> partials (pq_partial, nblk_pq per rhs) and the ||r||^2 partials go to

@@ -1667,7 +1667,7 @@ int fcg_nn_solve(hisq_ctx *ctx, double mass, int n, const void *b, void *x,
     RETCHK(launch_dot_partials(ctx, HISQ_F32, n, p, r, partial2, &nb2));
     RETCHK(fcg_alpha(ctx, partial, nblk_d, partial2, nb2, S, n));
     RETCHK(fcg_update_xr(ctx, xh, r, p, q, S, n, partial));
-    RETCHK(cg_reduce_beta(ctx, partial, S, n, tol2));
+    RETCHK(cg_reduce_beta(ctx, partial, blas_nblk(ctx), S, n, tol2));
     RETCHK(nn_apply_internal(ctx, n, static_cast<const float2 *>(r), static_cast<float2 *>(z)));
     RETCHK(launch_dot_partials(ctx, HISQ_F32, n, q, z, partial2, &nb2));
     RETCHK(fcg_beta(ctx, partial2, nb2, S, n));

@@ -228,14 +228,16 @@ STUDY = {
 
 
 def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, variants=None,
-                 plain=None, progress_tag=None):
+                 plain=None, progress_tag=None, nn_seeds=None):
     """48^3x12 (16 Z2 rhs, m = 0.01) or 64^3x16 (32 Gaussian rhs, m = 0.005): CG seconds per rhs
     to a true FP64 residual 1e-8 for mixed precision (FP16 and FP32 links), plain FP64 (48^3x12)
     and the flexible CG with the learned preconditioner (trained here on pairs harvested from plain
     CG on the same links), with iterations, peak device memory, the Dslash Gflop/s inside each
     solve and the cost of one network application.  `variants`: (form, layers) of the networks to
     train and solve with (default: the Gram form with 4 layers); `fcg_link_precs`: the link copies
-    the flexible CG's inner operator is run with (the faster is its result)."""
+    the flexible CG's inner operator is run with (the faster is its result); `nn_seeds`: seeds of
+    the networks' initial weights and training batches, each variant trained once per seed
+    (default: the workload's seed)."""
     import ctypes
     st = STUDY[name]
     cfg = synth.WORKLOADS[name]
@@ -317,9 +319,13 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
     if nf != n:
         out[ref_label] = solve(ref_label, bf, kind=hisq.HISQ_CG_MIXED, link_prec=best[1])
     out["learned"] = {}
-    for form, layers in variants:
-        key = f"{form}_L{layers}"
-        hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, layers, 8, seed))
+    runs = [(form, layers, s) for s in (nn_seeds or [None]) for form, layers in variants]
+    first_key = None
+    for form, layers, nn_seed in runs:
+        key = f"{form}_L{layers}" + ("" if nn_seed is None else f"_seed{nn_seed}")
+        first_key = first_key or key
+        tseed = seed if nn_seed is None else nn_seed
+        hisq._check(lat.ctx, lib.hisq_nn_init(lat.ctx, layers, 8, tseed))
         hisq._check(lat.ctx, lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM if form == "gram"
                                                   else hisq.HISQ_NN_FORM_DIRECT))
         hisq._check(lat.ctx, lib.hisq_nn_set_loss(lat.ctx, hisq.HISQ_NN_LOSS_RESIDUAL, mass))
@@ -335,8 +341,9 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
         progress(f"train the network {key}")
         t = time.perf_counter()
         hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, npairs.value, hisq._ptr(r), hisq._ptr(y),
-                                               epochs, batch, lr, seed, hist))
-        v = {"form": form, "layers": layers, "channels": 8, "loss": "residual", "init_scale": round(c, 5),
+                                               epochs, batch, lr, tseed, hist))
+        v = {"form": form, "layers": layers, "seed": tseed, "channels": 8, "loss": "residual",
+             "init_scale": round(c, 5),
              "epochs": epochs, "batch": batch, "lr": lr, "bf16": True,
              "training_s": round(time.perf_counter() - t, 2),
              "loss_first": round(hist[0], 5), "loss_last": round(hist[epochs - 1], 5)}
@@ -356,7 +363,7 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
         # a network whose flexible CG needs more than 1.5 x the mixed solver's iterations has lost
         # (and a non-Hermitian direct-form network may converge slowly): the solve stops there and
         # reports how far it got
-        cap = int(1.5 * out[ref_label]["iters_max"]) if len(variants) > 1 else 60000
+        cap = int(1.5 * out[ref_label]["iters_max"]) if len(runs) > 1 else 60000
         for lp in fcg_link_precs:
             lab = "f16links" if lp == hisq.HISQ_F16 else "f32links"
             v["fcg_" + lab] = solve(f"fcg_{key}_{lab}", bf, max_iter=cap, kind=hisq.HISQ_FCG_NN, link_prec=lp)
@@ -365,9 +372,8 @@ def solver_study(name, torch, synth, hisq, pm, epochs=0, fcg_link_precs=None, va
         v["speedup_vs_mixed"] = round(out[ref_label]["seconds"] / v[fbest]["seconds"], 3)
         v["iteration_ratio_vs_mixed"] = round(v[fbest]["iters_mean"] / out[ref_label]["iters_mean"], 3)
         out["learned"][key] = v
-    lead = out["learned"][f"{variants[0][0]}_L{variants[0][1]}"]
-    out["fcg_learned"] = dict(lead[lead["fcg_best"]], network=f"{variants[0][0]}_L{variants[0][1]}",
-                              link_copy=lead["fcg_best"][4:])
+    lead = out["learned"][first_key]
+    out["fcg_learned"] = dict(lead[lead["fcg_best"]], network=first_key, link_copy=lead["fcg_best"][4:])
     out["fcg_reference"] = ref_label
     out["speedup_fcg_vs_mixed"] = lead["speedup_vs_mixed"]
     out["iteration_ratio_fcg_vs_mixed"] = lead["iteration_ratio_vs_mixed"]
@@ -563,6 +569,9 @@ def main():
     ap.add_argument("--nn-variants", default="",
                     help="solver study: networks to train and solve with, as form:layers pairs, e.g. "
                          "gram:4,gram:2,direct:4 (default gram:4)")
+    ap.add_argument("--nn-seeds", default="",
+                    help="--workload c3|c4: train each network once per seed (comma-separated) to see "
+                         "how the learned preconditioner varies with its initial weights and batches")
     ap.add_argument("--no-c3", action="store_true",
                     help="leave out the 48^3x12 solver comparison of the default run")
     ap.add_argument("--profile", action="store_true",
@@ -676,8 +685,9 @@ def main():
         if args.nn_variants:
             variants = [(f.split(":")[0], int(f.split(":")[1])) for f in args.nn_variants.split(",")]
         links = {"both": None, "f32": (hisq.HISQ_F32,), "f16": (hisq.HISQ_F16,)}[args.fcg_links]
+        seeds = [int(v) for v in args.nn_seeds.split(",")] if args.nn_seeds else None
         print(json.dumps(solver_study(args.workload, torch, synth, hisq, pm, epochs=args.epochs,
-                                      fcg_link_precs=links, variants=variants)))
+                                      fcg_link_precs=links, variants=variants, nn_seeds=seeds)))
         return
     cfg = synth.WORKLOADS["c1"]
     dims, n = cfg["dims"], args.nrhs

@@ -596,9 +596,9 @@ def main():
     ap.add_argument("--profile-nn", action="store_true",
                     help="only the learned preconditioner's Gram application at 48^3x12 on 16 rhs, "
                          "2 + --steps times (for a rocprofv3 run)")
-    ap.add_argument("--profile-cg-workload", default="c2", choices=["c2", "c4"],
+    ap.add_argument("--profile-cg-workload", default="c2", choices=["c2", "c3", "c4"],
                     help="--profile-cg: the 32^3x8 CG to convergence (c2), or --steps iterations of "
-                         "the 64^3x16 mixed CG on 32 rhs (c4)")
+                         "the 48^3x12 mixed CG on 16 rhs (c3) or the 64^3x16 one on 32 rhs (c4)")
     ap.add_argument("--cg-naik-recon", type=int, default=18, choices=[18, 14, 13, 9],
                     help="reals per stored Naik link of the FP32 and FP16 copies in the 32^3x8 CG "
                          "(default run and --profile-cg)")
@@ -626,11 +626,11 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    if args.profile_cg and args.profile_cg_workload == "c4":
-        # the mixed CG's kernels where no cache level holds the vectors: 64^3 x 16, 32 rhs, FP32
-        # links, a fixed number of iterations (tiled links: the per-kernel traffic does not depend
-        # on the link values or on convergence)
-        c4 = synth.WORKLOADS["c4"]
+    if args.profile_cg and args.profile_cg_workload in ("c3", "c4"):
+        # the mixed CG's kernels where no cache level holds the vectors: 48^3 x 12 with 16 rhs or
+        # 64^3 x 16 with 32 rhs, FP32 links, a fixed number of iterations (tiled links: the
+        # per-kernel traffic does not depend on the link values or on convergence)
+        c4 = synth.WORKLOADS[args.profile_cg_workload]
         fat4, naik4 = synth.tiled_gauge_links(c4["dims"], 7)
         lat4 = hisq.Lattice(c4["dims"], 0)
         lat4.load_links(fat4, naik4, hisq.HISQ_LINKS_ALL, 18)

@@ -537,7 +537,9 @@ extern "C" int hisq_nn_harvest(hisq_ctx *ctx, double mass, int n, const void *b,
   CGState *S = static_cast<CGState *>(sp);
   CGState *hS = static_cast<CGState *>(hp);
   double *partial = static_cast<double *>(pp);
-  hisq_cg_params prm{HISQ_CG_F64, tol, 1000000, 50, HISQ_F32, 0, 8};
+  // the snapshots need the bundle in the caller's order: no repacking (cg_solve also skips it
+  // whenever it takes snapshots)
+  hisq_cg_params prm{HISQ_CG_F64, tol, 1000000, 50, HISQ_F32, 0, 8, 1};
   int taken = 0;
   // x snapshots go straight into y_out; r_k and y_k = x* - x_k are formed afterwards
   int rc = cg_solve(ctx, mass, n, b, xstar, &prm, nullptr, S, hS, partial, y_out, n_snap,

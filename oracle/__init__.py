@@ -16,6 +16,6 @@ differences), see the pin tests.
 from .dslash import (  # noqa: F401
     dslash_full, dslash_half, dslash_sites, embed, extract, m_ee, parity_lex, site_coords,
 )
-from .cg import cg, true_residual  # noqa: F401
+from .cg import cg, fcg, true_residual  # noqa: F401
 from . import nn  # noqa: F401
 from . import trace  # noqa: F401

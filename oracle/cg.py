@@ -74,3 +74,46 @@ def cg(fat, naik, b, dims, mass, tol, max_iter=100000, x0=None, max_restarts=5):
                 break
         x[i] = xi
     return x, iters, resid
+
+
+def fcg(fat, naik, b, dims, mass, tol, precond, max_iter=100000):
+    """Flexible CG with truncation 1 (Notay, SIAM J. Sci. Comput. 22 (2000) 1444), the solver the
+    learned preconditioner serves, with complex step sizes since a preconditioner need not be
+    Hermitian.  precond(r) -> z acts on one rhs [3][V/2].  For each rhs of b [n][3][V/2], from
+    x = 0:
+        r = b, z = P r, p = z
+        repeat: q = M p; alpha = <p, r> / <p, q>; x += alpha p; r -= alpha q;
+                stop when ||r|| <= tol ||b||; z = P r; beta = -<q, z> / <p, q>; p = z + beta p
+    (p is made M-orthogonal to the previous direction only).  Returns (x, iters, true_resid), the
+    true residual recomputed as ||b - M x|| / ||b||; no restart."""
+    b = np.asarray(b, np.complex128)
+    n = b.shape[0]
+    x = np.zeros_like(b)
+    iters = np.zeros(n, np.int64)
+    resid = np.zeros(n)
+
+    def apply(v):
+        return m_ee(fat, naik, v[None], dims, mass)[0]
+
+    for i in range(n):
+        bnorm = np.linalg.norm(b[i])
+        if bnorm == 0.0:
+            continue
+        xi = np.zeros_like(b[i])
+        r = b[i].copy()
+        p = np.asarray(precond(r), np.complex128)
+        while np.linalg.norm(r) > tol * bnorm and iters[i] < max_iter:
+            q = apply(p)
+            pq = _dot(p, q)
+            alpha = _dot(p, r) / pq
+            xi = xi + alpha * p
+            r = r - alpha * q
+            iters[i] += 1
+            if np.linalg.norm(r) <= tol * bnorm:
+                break
+            z = np.asarray(precond(r), np.complex128)
+            beta = -_dot(q, z) / pq
+            p = z + beta * p
+        x[i] = xi
+        resid[i] = np.linalg.norm(b[i] - apply(xi)) / bnorm
+    return x, iters, resid

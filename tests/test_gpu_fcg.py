@@ -157,3 +157,43 @@ def test_trained_network_gain(form, loss_kind):
         assert sum(ti["fell_back"]) == 0
         assert np.mean(ti["iters"]) < 0.8 * np.mean(ui["iters"])
     lat.close()
+
+
+def test_fcg_matches_the_oracle_fcg_with_the_same_network():
+    """The GPU flexible CG (FP32 body and network activations, FP64 reliable updates) against the
+    oracle's FP64 flexible CG with the oracle network as its preconditioner (Gram form, the same
+    weights: the identity network plus complex noise): the iteration counts agree to within the
+    rounding of the FP32 body, and both solutions meet tol in the oracle's true residual."""
+    from oracle import nn as onn
+    dims, mass, tol, layers = (6, 4, 4, 8), 0.3, 1e-8, 2
+    lat, fat, naik = make_lattice(dims, 410)
+    lib = hisq.library()
+    assert lib.hisq_nn_init(lat.ctx, layers, 8, 3) == 0
+    assert lib.hisq_nn_set_precision(lat.ctx, 0) == 0
+    assert lib.hisq_nn_set_form(lat.ctx, hisq.HISQ_NN_FORM_GRAM) == 0
+    k = lib.hisq_nn_num_params(lat.ctx)
+    assert k == onn.n_params(8, layers)
+    th = np.zeros(k, complex)
+    th[0] = 1.0                      # W_in[0]
+    th[8] = 1.0                      # layer 1: a[0][0]
+    th[8 + 72] = 1.0                 # layer 2: W[0][0]
+    th[8 + 72 + 64] = 1.0            # layer 2: a[0][0]
+    th[8 + 72 + 64 + 72] = 1.0       # W_out[0]
+    g = np.random.default_rng(412)
+    th = th + 0.1 * (g.standard_normal(k) + 1j * g.standard_normal(k))
+    _set(lib, lat.ctx, th)
+    b = synth.sources(dims, 2, 411)
+    x, info = lat.cg(mass, torch.from_numpy(b).to(DEV), kind=hisq.HISQ_FCG_NN, tol=tol,
+                     link_prec=hisq.HISQ_F32)
+    assert info["rc"] == 0 and info["fell_back"] == [0, 0], info
+
+    def precond(r):
+        return onn.apply(th, fat, r, dims, 8, layers, "gram")
+
+    xo, ito, ro = oracle.fcg(fat, naik, b, dims, mass, tol, precond)
+    res = oracle.true_residual(fat, naik, x.cpu().numpy(), b, dims, mass)
+    print(f"FCG iterations: GPU {info['iters']}, oracle {list(ito)}; true residuals {res}, oracle {ro}")
+    assert np.all(res <= tol) and np.all(ro <= tol)
+    for a, c in zip(info["iters"], ito):
+        assert abs(a - int(c)) <= 0.1 * c + 3
+    lat.close()

@@ -279,3 +279,26 @@ def init_params(channels: int, layers: int, seed: int, scale: float = 0.1) -> np
         if l >= 1:
             p["W"][l - 1][0, 0] += 1.0
     return pack(p)
+
+
+def adam(theta, grad_fn, steps: int, lr: float, b1: float = 0.9, b2: float = 0.999,
+         eps: float = 1e-8) -> np.ndarray:
+    """`steps` Adam updates (Kingma and Ba 2014, Algorithm 1, with their default beta1, beta2,
+    epsilon) of the complex parameters theta, grad_fn(theta) giving the Wirtinger gradient
+    dL/dRe + i dL/dIm.  Reading for complex parameters: Adam runs on the reals (Re, Im of every
+    parameter) as independent coordinates, so the gradient of coordinate Re w is Re grad(w) and
+    that of Im w is Im grad(w); the moments are kept per real coordinate."""
+    th = np.array(theta, complex)
+    x = np.concatenate([th.real, th.imag])
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    n = th.size
+    for t in range(1, steps + 1):
+        g = grad_fn(x[:n] + 1j * x[n:])
+        gr = np.concatenate([g.real, g.imag])
+        m = b1 * m + (1 - b1) * gr
+        v = b2 * v + (1 - b2) * gr * gr
+        mhat = m / (1 - b1 ** t)
+        vhat = v / (1 - b2 ** t)
+        x = x - lr * mhat / (np.sqrt(vhat) + eps)
+    return x[:n] + 1j * x[n:]

@@ -231,3 +231,49 @@ def test_save_load_keeps_the_form(tmp_path):
     assert np.array_equal(z1, z2)
     assert lib.hisq_nn_set_form(lat.ctx, 2) == hisq.HISQ_ERR_ARG
     lat.close()
+
+
+def test_training_steps_match_oracle_adam():
+    """Two epochs of hisq_nn_train on one minibatch of two pairs (two Adam steps on the same
+    pairs, FP32 activations, solution loss) against the oracle's Adam on the oracle's Wirtinger
+    gradient: the recorded losses match the oracle's at the start of each step, and every real
+    parameter whose starting gradient is not near zero ends where the oracle's does, to 1e-3 of
+    a step.  (Near-zero gradient components take their sign from FP32 rounding on the GPU.)"""
+    lat, fat, naik = make_lattice(DIMS, 330)
+    _init(lat, False)
+    lib = hisq.library()
+    th0 = _theta(331, scale=0.3).astype(np.complex64).astype(complex)  # the FP32 master weights
+    _set(lat, th0)
+    r = synth.sources(DIMS, 2, 332)
+    y = synth.sources(DIMS, 2, 333)
+    lr = 1e-2
+    hist = (hisq.ctypes.c_double * 2)()
+    tr = torch.from_numpy(r).to(DEV)
+    ty = torch.from_numpy(y).to(DEV)
+    hisq._check(lat.ctx, lib.hisq_nn_train(lat.ctx, 2, hisq._ptr(tr), hisq._ptr(ty), 2, 2, lr, 5, hist))
+    n = th0.size
+    w = (hisq.ctypes.c_double * (2 * n))()
+    hisq._check(lat.ctx, lib.hisq_nn_get_params(lat.ctx, w, 2 * n))
+    wv = np.array(list(w))
+    th_gpu = wv[0::2] + 1j * wv[1::2]
+
+    def grad(th):
+        return onn.loss_and_grad(th, fat, list(r), list(y), DIMS, 8, L)[1]
+
+    th1 = onn.adam(th0, grad, 1, lr)
+    th2 = onn.adam(th0, grad, 2, lr)
+    l0 = onn.loss(th0, fat, list(r), list(y), DIMS, 8, L)
+    l1 = onn.loss(th1, fat, list(r), list(y), DIMS, 8, L)
+    print(f"losses GPU {hist[0]:.6f} {hist[1]:.6f}, oracle {l0:.6f} {l1:.6f}")
+    assert abs(hist[0] - l0) <= 1e-5 * l0 and abs(hist[1] - l1) <= 1e-5 * l1
+    g0 = grad(th0)
+    g_re = np.concatenate([g0.real, g0.imag])
+    d = np.concatenate([(th_gpu - th2).real, (th_gpu - th2).imag])
+    keep = np.abs(g_re) > 1e-2 * np.max(np.abs(g_re))
+    assert keep.mean() >= 0.7, keep.mean()
+    tol = 1e-3 * lr + 2e-7 * np.max(np.abs(th0))
+    print(f"Adam: {keep.sum()} of {keep.size} reals compared, max deviation {np.max(np.abs(d[keep])):.3g} "
+          f"(bound {tol:.3g}); all reals {np.max(np.abs(d)):.3g} against a step of {lr}")
+    assert np.max(np.abs(d[keep])) <= tol
+    assert np.max(np.abs(d)) <= 2.5 * lr
+    lat.close()

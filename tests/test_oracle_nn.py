@@ -184,3 +184,35 @@ def test_gram_form_is_hermitian_positive_and_adjoint_is_adjoint():
     pb = nn.apply(th, fat, b, DIMS, c, l, "gram")
     assert abs(np.vdot(b, pa) - np.conj(np.vdot(a, pb))) < 1e-11 * abs(np.vdot(b, pa))
     assert np.vdot(a, pa).real > 0 and abs(np.vdot(a, pa).imag) < 1e-11 * abs(np.vdot(a, pa))
+
+
+def test_adam_first_step_is_bias_corrected():
+    """Step 1 of Adam moves every real coordinate against its gradient by lr |g| / (|g| + eps)
+    (the bias corrections cancel the (1 - beta) factors); without them it would move by
+    lr (1 - b1) / sqrt(1 - b2) = 3.16 lr.  Real and imaginary parts move independently."""
+    g0 = np.array([3.0 - 0.5j, -2e-3 + 4.0j, 1e-9 + 0j])
+    th0 = np.array([0.5 + 0.25j, -1.0 + 0.0j, 2.0 - 1.0j])
+    lr = 1e-2
+    th1 = nn.adam(th0, lambda th: g0, 1, lr)
+    for part in (np.real, np.imag):
+        g = part(g0)
+        want = part(th0) - lr * g / (np.abs(g) + 1e-8)
+        assert np.allclose(part(th1), want, rtol=0, atol=1e-15)
+
+
+def test_adam_ignores_the_gradient_scale_and_descends_a_quadratic():
+    """Adam's steps do not depend on a positive scale of the loss (up to eps), and on the
+    complex quadratic L = sum |w - c|^2 (Wirtinger gradient 2 (w - c)) with coordinates of very
+    different curvature it reaches the minimum."""
+    c = np.array([1.0 + 2.0j, -0.5 + 0.1j, 3.0 - 1.0j])
+    k = np.array([1.0, 30.0, 300.0])
+
+    def grad(th, s=1.0):
+        return s * 2.0 * k * (th - c)
+
+    th0 = np.zeros(3, complex)
+    a = nn.adam(th0, grad, 25, 0.05)
+    b = nn.adam(th0, lambda th: grad(th, 1000.0), 25, 0.05)
+    assert np.allclose(a, b, rtol=0, atol=1e-7)
+    far = nn.adam(th0, grad, 3000, 0.01)
+    assert np.max(np.abs(far - c)) < 1e-3, far

@@ -296,8 +296,10 @@ int hisq_nn_apply(hisq_ctx *ctx, int n, int prec_io, const void *r, void *z);
  * dL/dRe + i dL/dIm, 2 * num_params reals, host) for n pairs r, y (device complex128
  * [n][3][V/2]).  loss and grad may be NULL.  Synchronises. */
 int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void *y, double *loss, double *grad);
-/* Train on n_pairs pairs (device complex128 [n_pairs][3][V/2] each) with Adam (lr, beta1 0.9,
- * beta2 0.999), minibatches of `batch` consecutive pairs visited in a seeded random order, for
+/* Train on n_pairs pairs (device complex128 [n_pairs][3][V/2] each) with Adam (Kingma and Ba:
+ * lr, beta1 0.9, beta2 0.999, eps 1e-8, on the real and imaginary parts of the parameters as
+ * separate coordinates, FP32 master weights), minibatches of `batch` consecutive pairs visited
+ * in a seeded random order, for
  * `epochs` passes.  loss_history (host, epochs doubles, may be NULL) receives the mean minibatch
  * loss of each epoch.  Synchronises. */
 int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const void *y, int epochs, int batch,

@@ -299,7 +299,8 @@ int hisq_nn_loss_grad(hisq_ctx *ctx, int n, const void *r, const void *y, double
 /* Train on n_pairs pairs (device complex128 [n_pairs][3][V/2] each) with Adam (Kingma and Ba:
  * lr, beta1 0.9, beta2 0.999, eps 1e-8, on the real and imaginary parts of the parameters as
  * separate coordinates, FP32 master weights), minibatches of `batch` consecutive pairs visited
- * in a seeded random order, for `epochs` passes.  loss_history (host, epochs doubles, may be
+ * in a seeded random order (n_pairs / batch whole minibatches; the remaining pairs are not used;
+ * batch <= HISQ_MAX_RHS), for `epochs` passes.  loss_history (host, epochs doubles, may be
  * NULL) receives the mean minibatch loss of each epoch.  Synchronises. */
 int hisq_nn_train(hisq_ctx *ctx, int n_pairs, const void *r, const void *y, int epochs, int batch,
                   double lr, unsigned long long seed, double *loss_history);

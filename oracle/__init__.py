@@ -8,7 +8,9 @@ Every function here is the plain definition written out with numpy, in float64/c
 no blocking, fusion or reordering beyond what the definition states.  Each cites the passage of
 Kaczmarek et al., "HISQ inverter on Intel Xeon Phi and NVIDIA GPUs" (PoS LATTICE2014), that it
 follows.  The pins that tie these functions to the paper and to mathematics independent of this
-code are in tests/test_oracle_pins.py.
+code are in tests/test_oracle_pins.py, test_oracle_fcg.py, test_oracle_nn.py and
+test_oracle_trace.py; tests/test_oracle_mutations.py checks that planted slips in a copy of this
+package fail them.
 
 Parity status: every function here is pinned (closed forms, invariants, dense LU, finite
 differences), see the pin tests.

@@ -4,7 +4,6 @@ against the dense whole-lattice operator, independence of the bundle size, and a
 import numpy as np
 import pytest
 
-import synth
 from gpu_helpers import make_lattice
 from oracle import trace as otrace
 
